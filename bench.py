@@ -1,0 +1,158 @@
+"""Throughput of the D2V16 MRT FD-LB step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One "step" is one time step of the whole hot path (ghosts, moments,
+equilibrium, M / relax / Minv collision, Lax-Wendroff convection, forward
+Euler) over the whole grid of the headline workload: the 4096 x 4096 Mach-5
+shock hitting a dense bubble, FP32 populations with FP64 collision
+(MRT_FP32_EQ64).  value = MLUPS (million lattice-site updates per second),
+populations already resident in HBM.  Extra fields report the FP64 form on
+the same grid, the 1024^2 2D Riemann problem, the batched shock tubes and the
+adjoint step, the roofline of the step kernel, and the oracle's CPU rate on a
+bounded sample.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0               # MI355X HBM3E, published
+BYTES_PER_SITE = {"fp64": 256, "fp32": 128, "fp32_eq64": 128}   # 16 reads + 16 writes
+
+
+def _events_time(stream, fn, nsteps):
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    fn(nsteps)
+    e1.record(stream)
+    e1.synchronize()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3
+
+
+def time_solver(case, precision, steps, warmup, autotune=True):
+    import torch
+
+    from paper_1004_5442_amd.solver import solver_for_case
+    s = solver_for_case(case, precision)
+    if autotune:
+        s.autotune(4)
+    s.step(warmup)
+    s.sync()
+    sec = _events_time(torch.cuda.current_stream(), s.step, steps)
+    s.sync()      # raises if the run went unhealthy
+    tile = s.tile()
+    s.close()
+    mlups = case.cells * steps / sec / 1e6
+    return {"mlups": mlups, "sec": sec, "ms_per_step": 1e3 * sec / steps, "tile": tile}
+
+
+def roofline(case, precision, r):
+    per_launch_bytes = BYTES_PER_SITE[precision] * case.cells
+    achieved = per_launch_bytes / (r["sec"] / r["steps"]) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "step_kernel", "bytes_per_site": BYTES_PER_SITE[precision]}
+
+
+def cpu_baseline(rows=512, steps=2):
+    """The FP64 oracle on a band of the headline workload (4096 x rows)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mrt
+    from paper_1004_5442_amd import workloads as W
+    case = W.shock_bubble(n=4096, ny=rows)
+    bcmap = {"periodic": 0, "eq": 1, "outflow": 2, "reflect": 3}
+    p = mrt.Params(gamma=case.gamma, s=case.s, dt=case.dt, dx=case.dx, dy=case.dy,
+                   bc=[bcmap[b] for b in case.bc], side_state=case.side_state)
+    with threadpool_limits(limits=1):
+        f = mrt.init_populations(case.rho, case.ux, case.uy, case.T, p)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f = mrt.step(f, p)
+        sec = time.perf_counter() - t0
+    assert np.isfinite(f).all()
+    return {"value": round(case.cells * steps / sec / 1e6, 4), "unit": "MLUPS", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{steps} steps of a 4096x{rows} band of the shock-bubble case (FP64 NumPy oracle, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
+              "decomposition is described in the design notes but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1004_5442_amd import workloads as W
+    torch.cuda.set_device(0)
+    n = 4096
+    head = W.shock_bubble(n=n)
+    prec = "fp32_eq64"
+    r = time_solver(head, prec, args.steps, args.warmup)
+    r["steps"] = args.steps
+    out = {
+        "metric": "MLUPS (million lattice-site updates per second) of the MRT FD-LB step",
+        "value": round(r["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage, f64 collision",
+        "data": "synthetic",
+        "config": {"workload": f"shock_bubble {n}x{n} (Mach-5 shock on a density-3 bubble, "
+                               f"gamma 1.4, Pr 0.71, reflect/inflow/outflow)",
+                   "cells": head.cells, "precision": prec, "tile_rows": r["tile"][0],
+                   "grid_blocks": r["tile"][1]},
+        "roofline": roofline(head, prec, r),
+    }
+    if not args.no_extra:
+        extra = {}
+        k = max(20, args.steps // 4)
+        r64 = time_solver(head, "fp64", k, 3)
+        r64["steps"] = k
+        extra["fp64_same_grid"] = {"mlups": round(r64["mlups"], 1),
+                                   "roofline_frac": roofline(head, "fp64", r64)["frac"]}
+        r32 = time_solver(head, "fp32", k, 3)
+        r32["steps"] = k
+        extra["fp32_same_grid"] = {"mlups": round(r32["mlups"], 1),
+                                   "roofline_frac": roofline(head, "fp32", r32)["frac"]}
+        rp = W.riemann2d(n=1024, seed=0)
+        for pr in ("fp32_eq64", "fp64"):
+            rr = time_solver(rp, pr, 2 * k, 5)
+            rr["steps"] = 2 * k
+            extra[f"riemann2d_1024_{pr}"] = {
+                "mlups": round(rr["mlups"], 1),
+                "effective_GBs": roofline(rp, pr, rr)["achieved"],
+                "note": "fits the 256 MB Infinity Cache: effective, not HBM, bandwidth"}
+        out["extra"] = extra
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,247 @@
+/*
+ * mrtlb.h -- C ABI of the MI355X (gfx950) D2V16 MRT finite-difference lattice
+ * Boltzmann library.
+ *
+ * The scheme is the one of Chen, Xu, Zhang, Li and Succi, "Multiple-relaxation-
+ * time lattice Boltzmann approach to compressible flows with flexible specific-
+ * heat ratio and Prandtl number" (EPL letter):
+ *   df_i/dt + v_ia df_i/dx_a = -Minv_il S_lk (fhat_k - fhat^eq_k)        (Eq. 3)
+ * on the 16-velocity Kataoka-Tsutahara set with the extra-dof parameter eta
+ * (section "Construction of energy-conserving MRT LB model"), the
+ * transformation matrix M and the equilibrium moments fhat^eq of the Appendix,
+ * forward-Euler time stepping and Lax-Wendroff space differencing (same
+ * section, last paragraph before Fig. 1), with R = 1.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns MRT_OK (0) or a negative MRT_E* code; no C++
+ *    exception crosses the ABI.  mrt_last_error() gives a message for the last
+ *    failure on a context (a pointer into the context, valid until the next
+ *    call on it).
+ *  - A context owns one grid and runs on one HIP stream (the caller's, or the
+ *    null stream).  Work is enqueued asynchronously on that stream unless a
+ *    function says it synchronises.  A context is not thread-safe.
+ *  - Grid fields are row-major ny x nx arrays (x fastest), cell-centred:
+ *    cell (i, j) sits at ((i + 1/2) dx, (j + 1/2) dy).
+ *  - Populations are stored structure-of-arrays: plane i (0..15) holds f_i for
+ *    every cell, f[i * plane + j * pitch + x]; pitch >= nx and
+ *    plane >= ny * pitch are chosen by the library (mrt_get_layout).  Velocity order: shell 1 (speed 1) and shell 2
+ *    (speed 6) as (+x, +y, -x, -y); shell 3 (sqrt(2)(+-1,+-1)) and shell 4
+ *    ((3/sqrt 2)(+-1,+-1)) as (++, -+, --, +-).
+ *  - Device pointers are plain HIP device addresses; host pointers are
+ *    ordinary host memory.  Buffers passed in stay owned by the caller.
+ */
+#ifndef MRTLB_H
+#define MRTLB_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MRT_OK          0
+#define MRT_EINVAL     -1   /* bad argument or parameter                          */
+#define MRT_EDEVICE    -2   /* a HIP call failed                                  */
+#define MRT_ESTATE     -3   /* call out of order (params or fields not set yet)   */
+#define MRT_EUNSTABLE  -4   /* a kernel saw NaN/Inf, rho <= 0 or T <= 0           */
+#define MRT_ENOMEM     -5   /* device allocation failed                           */
+
+/* precision of a context */
+#define MRT_FP64        0   /* FP64 storage and arithmetic                        */
+#define MRT_FP32        1   /* FP32 storage and arithmetic; conserved sums
+                               compensated                                        */
+#define MRT_FP32_EQ64   2   /* FP32 storage and Lax-Wendroff stencil; moments,
+                               equilibrium, relaxation and Minv in FP64           */
+
+/* boundary kinds, one per side in the order x-lo, x-hi, y-lo, y-hi */
+#define MRT_BC_PERIODIC 0   /* both sides of an axis must be periodic             */
+#define MRT_BC_EQ       1   /* ghost = f^eq of a fixed state: the paper's
+                               f_i = f_i^eq on boundary nodes (section (b)), also
+                               used for inflow (section (d))                      */
+#define MRT_BC_OUTFLOW  2   /* ghost = copy of the adjacent interior cell         */
+#define MRT_BC_REFLECT  3   /* ghost = f^eq of the mirror-image interior cell with
+                               its normal velocity reversed (section (d))         */
+
+typedef struct mrt_ctx mrt_ctx;
+typedef struct mrt_batch mrt_batch;
+
+/* Scheme parameters (copied by mrt_set_params). */
+typedef struct mrt_params {
+    double gamma;          /* specific-heat ratio; b = 2/(gamma-1) dof, the
+                              extra (b-2) carried by eta; 1 < gamma <= 2           */
+    double Pr;             /* if > 0: s[7] = s[8] = Pr * s[5] (Pr = s_8/s_6 from
+                              Eqs. 12b-12d) and s[6] must equal s[5]              */
+    double s[16];          /* relaxation rates s_1..s_16 (s[k-1] = s_k).  s_1..4
+                              multiply collision invariants and are ignored;
+                              s_5..16 must lie in [0, 1/dt] (text after Eq. 12d) */
+    double dt, dx, dy;     /* time step and cell sizes, all > 0                   */
+    double eta0;           /* eta on shell 1; the paper fixes 5/2 and so does this
+                              library (any other value: MRT_EINVAL)              */
+    double side_state[4][4]; /* (rho, ux, uy, T) of each MRT_BC_EQ side           */
+} mrt_params;
+
+/* ---------------------------------------------------------------- grid */
+
+/* Create a context for an nx x ny grid.
+ * precision: MRT_FP64 / MRT_FP32 / MRT_FP32_EQ64.
+ * bc[4]:     boundary kinds (x-lo, x-hi, y-lo, y-hi); periodic sides must pair.
+ * f_dev:     NULL: the library allocates two population buffers;
+ *            else two caller-owned device buffers f_dev[0], f_dev[1], each of
+ *            mrt_population_bytes(nx, ny, precision) bytes, which must outlive
+ *            the context.
+ * stream:    hipStream_t to run on (NULL = null stream).
+ * Errors: MRT_EINVAL (nx, ny < 1, bad precision or bc), MRT_ENOMEM,
+ * MRT_EDEVICE.  On error *out is NULL. */
+int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
+                  void* const f_dev[2], void* stream);
+
+/* Bytes of one population buffer for a grid (16 planes, padded pitch). */
+long long mrt_population_bytes(int nx, int ny, int precision);
+
+/* Row pitch (elements) and plane stride (elements) of the population layout. */
+int mrt_get_layout(const mrt_ctx* ctx, long long* pitch, long long* plane);
+
+/* Validate and copy parameters (see mrt_params).  Computes the ghost
+ * equilibria of MRT_BC_EQ sides.  Errors: MRT_EINVAL. */
+int mrt_set_params(mrt_ctx* ctx, const mrt_params* p);
+
+/* Initialise the populations to the local equilibrium of the given fields,
+ * f = Minv fhat^eq(rho, u, T) (the equilibrium of section (b), used at t = 0).
+ * rho, ux, uy, T: ny*nx doubles, host memory (on_device = 0) or device memory
+ * (on_device = 1).  Host input is staged and the call synchronises the stream.
+ * Errors: MRT_ESTATE (params unset), MRT_EINVAL (rho <= 0 or T <= 0 seen;
+ * host input only). */
+int mrt_set_fields(mrt_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                   const double* T, int on_device);
+
+/* Advance n time steps (Eq. 3, forward Euler, Lax-Wendroff).  Asynchronous.
+ * Health (NaN, rho <= 0, T <= 0) is recorded on the device and reported by
+ * the next synchronising call.  Errors: MRT_ESTATE, MRT_EINVAL (n < 0). */
+int mrt_step(mrt_ctx* ctx, int n);
+
+/* Macroscopic fields of the current populations: rho = fhat_1, u = j/rho,
+ * T = (e - rho u^2)/(b rho) (R = 1).  Outputs ny*nx doubles on the host
+ * (on_device = 0; the call synchronises) or on the device (on_device = 1;
+ * asynchronous).  Any output pointer may be NULL.
+ * Errors: MRT_ESTATE, MRT_EUNSTABLE (health flag set since the last check;
+ * the outputs are still written). */
+int mrt_read_moments(mrt_ctx* ctx, double* rho, double* ux, double* uy, double* T,
+                     int on_device);
+
+/* Copy the current populations out / in, converted to FP64, in the unpadded
+ * layout f[(i * ny + j) * nx + x] (16*ny*nx doubles).  Host memory
+ * (on_device = 0, synchronises) or device memory (on_device = 1). */
+int mrt_get_populations(mrt_ctx* ctx, double* f, int on_device);
+int mrt_set_populations(mrt_ctx* ctx, const double* f, int on_device);
+
+/* Raw device pointer of the current population buffer (storage precision,
+ * padded layout) and of the other (scratch) buffer. */
+int mrt_current_buffer(mrt_ctx* ctx, void** cur, void** other);
+
+/* Synchronise the stream and test the health flag (MRT_EUNSTABLE if set;
+ * the flag is cleared). */
+int mrt_sync(mrt_ctx* ctx);
+
+/* Tile shape of the step kernel: rows per work item (>= 1) and workgroups
+ * launched (0 = one per work item).  The defaults come from mrt_autotune. */
+int mrt_set_tile(mrt_ctx* ctx, int rows_per_item, int grid_blocks);
+int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
+
+/* Time candidate tile shapes on the current state (the populations are saved
+ * and restored) and keep the fastest.  Synchronises. */
+int mrt_autotune(mrt_ctx* ctx, int steps_per_trial);
+
+void mrt_destroy(mrt_ctx* ctx);
+const char* mrt_last_error(const mrt_ctx* ctx);
+
+/* ------------------------------------------------------------- adjoint
+ * Discrete adjoint of one step on a fully periodic grid (other boundary kinds:
+ * MRT_EINVAL).  With F the one-step map f^{n+1} = F(f^n; s):
+ *   lam_n = (dF/df^n)^T lam_next
+ *   ds[k] += sum over cells and populations of lam_next * dF/ds_k,
+ *            dF/ds_k = -dt Minv[:,k] (fhat_k - fhat^eq_k)      (derived from Eq. 3)
+ * lam_next, f_n, lam_n: device buffers in the context's storage precision and
+ * padded layout (as mrt_current_buffer).  ds: 16 device doubles, accumulated
+ * (the caller zeroes it).  Asynchronous.  lam_n must not alias lam_next. */
+int mrt_adjoint_step(mrt_ctx* ctx, const void* lam_next, const void* f_n, void* lam_n,
+                     double* ds);
+
+/* One forward step between explicit device buffers (storage precision,
+ * padded layout), without touching the context's own buffers: used to
+ * recompute states from checkpoints.  Asynchronous. */
+int mrt_step_buffers(mrt_ctx* ctx, const void* f_in, void* f_out);
+
+/* Density of an explicit population buffer: rho[j*nx+x] = sum_i f_i (device
+ * doubles).  Asynchronous. */
+int mrt_density(mrt_ctx* ctx, const void* f, double* rho);
+
+/* Adjoint of mrt_density: lam_i = g_rho for all 16 populations (device
+ * buffers).  Asynchronous. */
+int mrt_density_adjoint(mrt_ctx* ctx, const double* g_rho, void* lam);
+
+/* Adjoint of mrt_set_fields (f^0 = Minv fhat^eq(rho, u, T)): given lam0 and
+ * the device fields, writes g_x[j*nx+x] = sum_i lam0_i df^0_i/dx for x in
+ * (rho, ux, uy, T).  Any output may be NULL.  Asynchronous. */
+int mrt_init_adjoint(mrt_ctx* ctx, const void* lam0, const double* rho, const double* ux,
+                     const double* uy, const double* T, double* g_rho, double* g_ux,
+                     double* g_uy, double* g_T);
+
+/* Initialise an explicit population buffer from device fields (as
+ * mrt_set_fields with on_device = 1, but into f).  Asynchronous. */
+int mrt_init_buffer(mrt_ctx* ctx, const double* rho, const double* ux, const double* uy,
+                    const double* T, void* f);
+
+/* -------------------------------------------------------------- batch
+ * Many independent grids (e.g. shock tubes of different length, gamma, Pr and
+ * Mach) advanced together: every step of every instance runs in one kernel
+ * launch over a table of (instance, tile) work items, and mrt_batch_step(n)
+ * replays one captured HIP graph of n launches.  Storage precision is the
+ * batch's; each instance has its own nx, ny, boundary kinds and parameters. */
+typedef struct mrt_instance {
+    int nx, ny;
+    int bc[4];
+    mrt_params params;
+} mrt_instance;
+
+/* Errors: MRT_EINVAL (count < 1, any instance invalid), MRT_ENOMEM. */
+int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int precision,
+                     void* stream);
+/* Fields of instance i (host doubles, ny*nx each).  Synchronises. */
+int mrt_batch_set_fields(mrt_batch* b, int i, const double* rho, const double* ux,
+                         const double* uy, const double* T);
+int mrt_batch_step(mrt_batch* b, int n);
+/* Moments of instance i to host doubles (any may be NULL).  Synchronises;
+ * MRT_EUNSTABLE if any instance went unhealthy. */
+int mrt_batch_read_moments(mrt_batch* b, int i, double* rho, double* ux, double* uy, double* T);
+/* Unpadded FP64 populations of instance i (16*ny*nx host doubles). */
+int mrt_batch_get_populations(mrt_batch* b, int i, double* f);
+/* Rows per work item (each work item is 64 columns wide) and workgroups
+ * launched (0 = one wave per work item); autotune times candidates on the
+ * current state (saved and restored) and keeps the fastest.  Changing the
+ * tile drops the captured graphs. */
+int mrt_batch_set_tile(mrt_batch* b, int rows_per_item, int grid_blocks);
+int mrt_batch_get_tile(const mrt_batch* b, int* rows_per_item, int* grid_blocks);
+int mrt_batch_autotune(mrt_batch* b, int steps_per_trial);
+long long mrt_batch_cells(const mrt_batch* b);
+void mrt_batch_destroy(mrt_batch* b);
+const char* mrt_batch_last_error(const mrt_batch* b);
+
+/* ------------------------------------------------------ host utilities
+ * The library's own transform code evaluated on the host in FP64 (the
+ * kernels run the same templates).  They need no GPU.
+ *  mrt_host_transform: which = 0: out = M in (populations -> moments, the
+ *    Appendix rows); 1: out = Minv in; 2: out = M^T in; 3: out = Minv^T in.
+ *  mrt_host_equilibrium: f = Minv fhat^eq(rho, u, T) (Appendix), R = 1.
+ *  mrt_host_collision: out = dt Minv diag(s) (M f - fhat^eq)   (Eq. 3).
+ *  mrt_host_cell_adjoint: coll = dt (dC/df)^T lam at one cell, and
+ *    dsk[k] = dt (fhat_k - fhat^eq_k)(Minv^T lam)_k.
+ * Arrays are 16 doubles; s holds s_1..s_16.  MRT_EINVAL on NULL or gamma<=1. */
+int mrt_host_transform(int which, const double* in, double* out);
+int mrt_host_equilibrium(double gamma, double rho, double ux, double uy, double T, double* f);
+int mrt_host_collision(double gamma, const double* s, double dt, const double* f, double* out);
+int mrt_host_cell_adjoint(double gamma, const double* s, double dt, const double* f,
+                          const double* lam, double* coll, double* dsk);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRTLB_H */

@@ -1,0 +1,861 @@
+// mrt_api.hip -- host side of the C ABI declared in include/mrtlb.h.
+//
+// Owns contexts and batches: parameter validation, population buffers, the
+// per-instance constant block (Inst) and the work-item table read by the
+// step kernel, the health flag, the tile autotuner and the captured HIP
+// graphs of the batched form.  All compute is in mrt_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "mrt_dual.h"
+#include "mrt_internal.h"
+#include "../../include/mrtlb.h"
+
+namespace mrt {
+hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
+                  void* fout, unsigned* health, int grid, hipStream_t st);
+hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
+                     const void* fn, void* lout, double* partial, double* ds, hipStream_t st);
+hipError_t k_init(int prec, const Inst* P, long long cells, const double* rho, const double* ux,
+                  const double* uy, const double* T, void* f, hipStream_t st);
+hipError_t k_moments(int prec, const Inst* P, long long cells, const void* f, double* rho,
+                     double* ux, double* uy, double* T, unsigned* health, hipStream_t st);
+hipError_t k_density(int prec, const Inst* P, long long cells, const void* f, double* rho,
+                     hipStream_t st);
+hipError_t k_density_adjoint(int prec, const Inst* P, long long cells, const double* g_rho,
+                             void* lam, hipStream_t st);
+hipError_t k_init_adjoint(int prec, const Inst* P, long long cells, const void* lam,
+                          const double* rho, const double* ux, const double* uy, const double* T,
+                          double* g_rho, double* g_ux, double* g_uy, double* g_T, hipStream_t st);
+hipError_t k_export(int prec, const Inst* P, long long cells, const void* f, double* out,
+                    hipStream_t st);
+hipError_t k_import(int prec, const Inst* P, long long cells, const double* in, void* f,
+                    hipStream_t st);
+}  // namespace mrt
+
+using mrt::Inst;
+using mrt::Item;
+
+namespace {
+
+size_t elem_size(int prec) { return prec == MRT_FP64 ? 8 : 4; }
+
+long long pitch_for(int nx) { return ((long long)nx + 63) / 64 * 64; }
+
+// Plane stride: rows * pitch plus an odd number of 64-element blocks, so the
+// 16 planes of one row do not sit at a large power-of-two distance apart.
+long long plane_for(int nx, int ny) { return (long long)ny * pitch_for(nx) + 5 * 64; }
+
+bool bc_ok(const int bc[4]) {
+    for (int k = 0; k < 4; ++k)
+        if (bc[k] < MRT_BC_PERIODIC || bc[k] > MRT_BC_REFLECT) return false;
+    if ((bc[0] == MRT_BC_PERIODIC) != (bc[1] == MRT_BC_PERIODIC)) return false;
+    if ((bc[2] == MRT_BC_PERIODIC) != (bc[3] == MRT_BC_PERIODIC)) return false;
+    return true;
+}
+
+// Validate parameters and fill the scheme constants of an instance.
+int fill_inst(Inst& I, int nx, int ny, const int bc[4], const mrt_params* p, std::string& err) {
+    if (!p) { err = "params is NULL"; return MRT_EINVAL; }
+    if (!(p->gamma > 1.0 && p->gamma <= 2.0)) { err = "gamma must lie in (1, 2]"; return MRT_EINVAL; }
+    if (!(p->dt > 0 && p->dx > 0 && p->dy > 0)) { err = "dt, dx, dy must be > 0"; return MRT_EINVAL; }
+    if (!(p->eta0 == 0.0 || p->eta0 == 2.5)) { err = "eta0 must be 5/2 (0 selects it)"; return MRT_EINVAL; }
+    double s[16];
+    for (int k = 0; k < 16; ++k) s[k] = p->s[k];
+    if (p->Pr > 0) {
+        if (std::fabs(s[6] - s[5]) > 1e-12 * std::max(1.0, std::fabs(s[5]))) {
+            err = "Pr > 0 needs s_7 == s_6";
+            return MRT_EINVAL;
+        }
+        s[7] = s[8] = p->Pr * s[5];
+    } else if (p->Pr < 0) {
+        err = "Pr must be >= 0";
+        return MRT_EINVAL;
+    }
+    for (int k = 4; k < 16; ++k) {
+        const double sd = s[k] * p->dt;
+        if (!(sd >= 0.0 && sd <= 1.0 + 1e-12)) {
+            char buf[96];
+            std::snprintf(buf, sizeof buf, "s_%d * dt = %g outside [0, 1]", k + 1, sd);
+            err = buf;
+            return MRT_EINVAL;
+        }
+    }
+    I.b = 2.0 / (p->gamma - 1.0);
+    I.dt = p->dt;
+    for (int k = 0; k < 16; ++k) I.sdt[k] = k < 4 ? 0.0 : s[k] * p->dt;
+    const double h[2] = {p->dx, p->dy};
+    for (int a = 0; a < 2; ++a)
+        for (int k = 0; k < 4; ++k) {
+            const double c = mrt::shell_speed(k) * p->dt / h[a];
+            I.lw[a][k][0] = 0.5 * c * c - 0.5 * c;
+            I.lw[a][k][1] = 0.5 * c * c + 0.5 * c;
+            I.lwf[a][k][0] = float(I.lw[a][k][0]);
+            I.lwf[a][k][1] = float(I.lw[a][k][1]);
+        }
+    for (int side = 0; side < 4; ++side) {
+        I.bc[side] = bc[side];
+        for (int i = 0; i < 16; ++i) I.ghost[side][i] = 0.0;
+        if (bc[side] == MRT_BC_EQ) {
+            const double* st = p->side_state[side];
+            if (!(st[0] > 0 && st[3] > 0)) { err = "EQ side state needs rho > 0 and T > 0"; return MRT_EINVAL; }
+            mrt::equilibrium_pops<double>(st[0], st[1], st[2], st[3], I.b, I.ghost[side]);
+        }
+    }
+    (void)nx;
+    (void)ny;
+    return MRT_OK;
+}
+
+// Work items of one instance: 64-column strips x bands of `rows` rows.
+void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
+    for (int y0 = 0; y0 < ny; y0 += rows)
+        for (int x0 = 0; x0 < nx; x0 += 64)
+            items.push_back(Item{inst, x0, y0, std::min(ny, y0 + rows)});
+}
+
+int default_rows(int nx, int ny) {
+    const long long strips = (nx + 63) / 64;
+    long long r = (strips * ny + 8191) / 8192;
+    r = std::max<long long>(4, std::min<long long>(r, 256));
+    return int(std::min<long long>(r, ny));
+}
+
+}  // namespace
+
+#define HIPTRY(call)                                                           \
+    do {                                                                       \
+        hipError_t e_ = (call);                                                \
+        if (e_ != hipSuccess) {                                                \
+            ctx_err = std::string(#call) + ": " + hipGetErrorString(e_);       \
+            return MRT_EDEVICE;                                                \
+        }                                                                      \
+    } while (0)
+
+struct mrt_ctx {
+    int nx = 0, ny = 0, prec = 0;
+    int bc[4] = {0, 0, 0, 0};
+    hipStream_t stream = nullptr;
+    void* f[2] = {nullptr, nullptr};
+    bool own_f = false;
+    int cur = 0;
+    long long pitch = 0, plane = 0;
+    Inst inst{};
+    Inst* d_inst = nullptr;
+    Item* d_items = nullptr;
+    int nitems = 0, rows = 0, grid = 0;
+    double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
+    double* d_partial = nullptr;     // 16 doubles per work item: adjoint partial sums
+    unsigned* d_health = nullptr;
+    bool params_set = false, fields_set = false;
+    std::string err;
+};
+
+namespace {
+
+int ctx_fail(mrt_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+int build_items(mrt_ctx* c, int rows) {
+    std::string& ctx_err = c->err;
+    std::vector<Item> items;
+    add_items(items, 0, c->nx, c->ny, rows);
+    if (c->d_items) HIPTRY(hipFree(c->d_items));
+    if (c->d_partial) HIPTRY(hipFree(c->d_partial));
+    c->d_items = nullptr;
+    c->d_partial = nullptr;
+    HIPTRY(hipMalloc(&c->d_items, items.size() * sizeof(Item)));
+    HIPTRY(hipMemcpy(c->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    HIPTRY(hipMalloc(&c->d_partial, items.size() * 16 * sizeof(double)));
+    c->nitems = int(items.size());
+    c->rows = rows;
+    return MRT_OK;
+}
+
+int check_health(mrt_ctx* c) {
+    std::string& ctx_err = c->err;
+    unsigned h = 0;
+    HIPTRY(hipMemcpyAsync(&h, c->d_health, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    if (h) {
+        HIPTRY(hipMemsetAsync(c->d_health, 0, sizeof(unsigned), c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+        c->err = "non-finite value, rho <= 0 or T <= 0 detected";
+        return MRT_EUNSTABLE;
+    }
+    return MRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+long long mrt_population_bytes(int nx, int ny, int precision) {
+    if (nx < 1 || ny < 1) return 0;
+    return 16LL * plane_for(nx, ny) * (long long)elem_size(precision);
+}
+
+int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
+                  void* const f_dev[2], void* stream) {
+    if (!out) return MRT_EINVAL;
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || precision < 0 || precision > 2 || !bc || !bc_ok(bc)) return MRT_EINVAL;
+    mrt_ctx* c = new mrt_ctx();
+    std::string& ctx_err = c->err;
+    c->nx = nx;
+    c->ny = ny;
+    c->prec = precision;
+    for (int k = 0; k < 4; ++k) c->bc[k] = bc[k];
+    c->stream = static_cast<hipStream_t>(stream);
+    c->pitch = pitch_for(nx);
+    c->plane = plane_for(nx, ny);
+    const size_t bytes = size_t(mrt_population_bytes(nx, ny, precision));
+    auto fail = [&](int code) {
+        mrt_destroy(c);
+        return code;
+    };
+    if (f_dev && f_dev[0] && f_dev[1]) {
+        c->f[0] = f_dev[0];
+        c->f[1] = f_dev[1];
+        c->own_f = false;
+    } else {
+        if (hipMalloc(&c->f[0], bytes) != hipSuccess || hipMalloc(&c->f[1], bytes) != hipSuccess)
+            return fail(MRT_ENOMEM);
+        c->own_f = true;
+    }
+    if (hipMalloc(&c->d_inst, sizeof(Inst)) != hipSuccess ||
+        hipMalloc(&c->d_health, sizeof(unsigned)) != hipSuccess ||
+        hipMalloc(&c->d_stage, 4 * sizeof(double) * size_t(nx) * ny) != hipSuccess)
+        return fail(MRT_ENOMEM);
+    if (hipMemset(c->d_health, 0, sizeof(unsigned)) != hipSuccess) return fail(MRT_EDEVICE);
+    // zero both buffers: pitch padding and the plane gaps are never read, but
+    // keep them defined
+    if (hipMemset(c->f[0], 0, bytes) != hipSuccess || hipMemset(c->f[1], 0, bytes) != hipSuccess)
+        return fail(MRT_EDEVICE);
+    c->inst.off = 0;
+    c->inst.plane = c->plane;
+    c->inst.nx = nx;
+    c->inst.ny = ny;
+    c->inst.pitch = int(c->pitch);
+    c->inst.item0 = 0;
+    for (int k = 0; k < 4; ++k) c->inst.bc[k] = bc[k];
+    if (build_items(c, default_rows(nx, ny)) != MRT_OK) return fail(MRT_EDEVICE);
+    (void)ctx_err;
+    *out = c;
+    return MRT_OK;
+}
+
+int mrt_get_layout(const mrt_ctx* c, long long* pitch, long long* plane) {
+    if (!c) return MRT_EINVAL;
+    if (pitch) *pitch = c->pitch;
+    if (plane) *plane = c->plane;
+    return MRT_OK;
+}
+
+int mrt_set_params(mrt_ctx* c, const mrt_params* p) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    Inst I = c->inst;
+    const int rc = fill_inst(I, c->nx, c->ny, c->bc, p, c->err);
+    if (rc != MRT_OK) return rc;
+    c->inst = I;
+    HIPTRY(hipMemcpyAsync(c->d_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    c->params_set = true;
+    return MRT_OK;
+}
+
+int mrt_set_fields(mrt_ctx* c, const double* rho, const double* ux, const double* uy,
+                   const double* T, int on_device) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    if (!rho || !ux || !uy || !T) return ctx_fail(c, MRT_EINVAL, "NULL field");
+    const long long n = (long long)c->nx * c->ny;
+    if (on_device) {
+        HIPTRY(mrt::k_init(c->prec, c->d_inst, n, rho, ux, uy, T, c->f[c->cur], c->stream));
+    } else {
+        for (long long k = 0; k < n; ++k)
+            if (!(rho[k] > 0 && T[k] > 0)) return ctx_fail(c, MRT_EINVAL, "rho and T must be > 0");
+        double* s = c->d_stage;
+        const size_t b = sizeof(double) * size_t(n);
+        HIPTRY(hipMemcpyAsync(s, rho, b, hipMemcpyHostToDevice, c->stream));
+        HIPTRY(hipMemcpyAsync(s + n, ux, b, hipMemcpyHostToDevice, c->stream));
+        HIPTRY(hipMemcpyAsync(s + 2 * n, uy, b, hipMemcpyHostToDevice, c->stream));
+        HIPTRY(hipMemcpyAsync(s + 3 * n, T, b, hipMemcpyHostToDevice, c->stream));
+        HIPTRY(mrt::k_init(c->prec, c->d_inst, n, s, s + n, s + 2 * n, s + 3 * n, c->f[c->cur], c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+    }
+    c->fields_set = true;
+    return MRT_OK;
+}
+
+int mrt_step(mrt_ctx* c, int n) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (n < 0) return ctx_fail(c, MRT_EINVAL, "n < 0");
+    if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
+    for (int k = 0; k < n; ++k) {
+        HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[c->cur], c->f[1 - c->cur],
+                           c->d_health, c->grid, c->stream));
+        c->cur ^= 1;
+    }
+    return MRT_OK;
+}
+
+int mrt_step_buffers(mrt_ctx* c, const void* fin, void* fout) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    if (!fin || !fout || fin == fout) return ctx_fail(c, MRT_EINVAL, "need two distinct buffers");
+    HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, fin, fout, c->d_health, c->grid,
+                       c->stream));
+    return MRT_OK;
+}
+
+int mrt_read_moments(mrt_ctx* c, double* rho, double* ux, double* uy, double* T, int on_device) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
+    const long long n = (long long)c->nx * c->ny;
+    if (on_device) {
+        HIPTRY(mrt::k_moments(c->prec, c->d_inst, n, c->f[c->cur], rho, ux, uy, T, c->d_health, c->stream));
+        return MRT_OK;
+    }
+    double* s = c->d_stage;
+    HIPTRY(mrt::k_moments(c->prec, c->d_inst, n, c->f[c->cur], s, s + n, s + 2 * n, s + 3 * n,
+                          c->d_health, c->stream));
+    const size_t b = sizeof(double) * size_t(n);
+    double* outs[4] = {rho, ux, uy, T};
+    for (int k = 0; k < 4; ++k)
+        if (outs[k]) HIPTRY(hipMemcpyAsync(outs[k], s + k * n, b, hipMemcpyDeviceToHost, c->stream));
+    return check_health(c);
+}
+
+int mrt_get_populations(mrt_ctx* c, double* f, int on_device) {
+    if (!c || !f) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    const long long n = (long long)c->nx * c->ny;
+    if (on_device) {
+        HIPTRY(mrt::k_export(c->prec, c->d_inst, n, c->f[c->cur], f, c->stream));
+        return MRT_OK;
+    }
+    double* tmp = nullptr;
+    HIPTRY(hipMallocAsync((void**)&tmp, sizeof(double) * 16 * size_t(n), c->stream));
+    HIPTRY(mrt::k_export(c->prec, c->d_inst, n, c->f[c->cur], tmp, c->stream));
+    HIPTRY(hipMemcpyAsync(f, tmp, sizeof(double) * 16 * size_t(n), hipMemcpyDeviceToHost, c->stream));
+    HIPTRY(hipFreeAsync(tmp, c->stream));
+    HIPTRY(hipStreamSynchronize(c->stream));
+    return MRT_OK;
+}
+
+int mrt_set_populations(mrt_ctx* c, const double* f, int on_device) {
+    if (!c || !f) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    const long long n = (long long)c->nx * c->ny;
+    if (on_device) {
+        HIPTRY(mrt::k_import(c->prec, c->d_inst, n, f, c->f[c->cur], c->stream));
+    } else {
+        double* tmp = nullptr;
+        HIPTRY(hipMallocAsync((void**)&tmp, sizeof(double) * 16 * size_t(n), c->stream));
+        HIPTRY(hipMemcpyAsync(tmp, f, sizeof(double) * 16 * size_t(n), hipMemcpyHostToDevice, c->stream));
+        HIPTRY(mrt::k_import(c->prec, c->d_inst, n, tmp, c->f[c->cur], c->stream));
+        HIPTRY(hipFreeAsync(tmp, c->stream));
+        HIPTRY(hipStreamSynchronize(c->stream));
+    }
+    c->fields_set = true;
+    return MRT_OK;
+}
+
+int mrt_current_buffer(mrt_ctx* c, void** cur, void** other) {
+    if (!c) return MRT_EINVAL;
+    if (cur) *cur = c->f[c->cur];
+    if (other) *other = c->f[1 - c->cur];
+    return MRT_OK;
+}
+
+int mrt_sync(mrt_ctx* c) {
+    if (!c) return MRT_EINVAL;
+    return check_health(c);
+}
+
+int mrt_set_tile(mrt_ctx* c, int rows, int grid) {
+    if (!c) return MRT_EINVAL;
+    if (rows < 1 || grid < 0) return ctx_fail(c, MRT_EINVAL, "rows >= 1, grid >= 0");
+    const int rc = build_items(c, std::min(rows, c->ny));
+    if (rc != MRT_OK) return rc;
+    c->grid = grid;
+    return MRT_OK;
+}
+
+int mrt_get_tile(const mrt_ctx* c, int* rows, int* grid) {
+    if (!c) return MRT_EINVAL;
+    if (rows) *rows = c->rows;
+    if (grid) *grid = c->grid;
+    return MRT_OK;
+}
+
+int mrt_autotune(mrt_ctx* c, int steps) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
+    if (steps < 1) steps = 4;
+    const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));
+    void* save = nullptr;
+    HIPTRY(hipMalloc(&save, bytes));
+    HIPTRY(hipMemcpyAsync(save, c->f[c->cur], bytes, hipMemcpyDeviceToDevice, c->stream));
+    hipEvent_t e0, e1;
+    HIPTRY(hipEventCreate(&e0));
+    HIPTRY(hipEventCreate(&e1));
+    int dev = 0, cus = 0;
+    HIPTRY(hipGetDevice(&dev));
+    HIPTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int row_opts[] = {4, 8, 16, 32, 64, 128, 256};
+    const int grid_mult[] = {0, 2, 4, 8};
+    float best = 1e30f;
+    int best_rows = c->rows, best_grid = c->grid;
+    for (int r : row_opts) {
+        if (r > c->ny && r != row_opts[0]) break;
+        if (build_items(c, std::min(r, c->ny)) != MRT_OK) return MRT_EDEVICE;
+        for (int gm : grid_mult) {
+            const int g = gm == 0 ? 0 : gm * cus;
+            if (g != 0 && g * 4 >= c->nitems) continue;
+            c->grid = g;
+            // warm-up, then timed
+            mrt_step(c, 1);
+            HIPTRY(hipEventRecord(e0, c->stream));
+            mrt_step(c, steps);
+            HIPTRY(hipEventRecord(e1, c->stream));
+            HIPTRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_rows = c->rows;
+                best_grid = g;
+            }
+            HIPTRY(hipMemcpyAsync(c->f[c->cur], save, bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    HIPTRY(hipStreamSynchronize(c->stream));
+    HIPTRY(hipEventDestroy(e0));
+    HIPTRY(hipEventDestroy(e1));
+    HIPTRY(hipFree(save));
+    HIPTRY(hipMemsetAsync(c->d_health, 0, sizeof(unsigned), c->stream));
+    if (build_items(c, best_rows) != MRT_OK) return MRT_EDEVICE;
+    c->grid = best_grid;
+    HIPTRY(hipStreamSynchronize(c->stream));
+    return MRT_OK;
+}
+
+void mrt_destroy(mrt_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->own_f) {
+        if (c->f[0]) (void)hipFree(c->f[0]);
+        if (c->f[1]) (void)hipFree(c->f[1]);
+    }
+    if (c->d_inst) (void)hipFree(c->d_inst);
+    if (c->d_items) (void)hipFree(c->d_items);
+    if (c->d_stage) (void)hipFree(c->d_stage);
+    if (c->d_partial) (void)hipFree(c->d_partial);
+    if (c->d_health) (void)hipFree(c->d_health);
+    delete c;
+}
+
+const char* mrt_last_error(const mrt_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
+
+// ---------------------------------------------------------------- adjoint
+
+static bool all_periodic(const mrt_ctx* c) {
+    for (int k = 0; k < 4; ++k)
+        if (c->bc[k] != MRT_BC_PERIODIC) return false;
+    return true;
+}
+
+int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* lam_n, double* ds) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
+    if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
+        return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
+    HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items, c->nitems, lam_next, f_n, lam_n,
+                          c->d_partial, ds, c->stream));
+    return MRT_OK;
+}
+
+int mrt_density(mrt_ctx* c, const void* f, double* rho) {
+    if (!c || !f || !rho) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    HIPTRY(mrt::k_density(c->prec, c->d_inst, (long long)c->nx * c->ny, f, rho, c->stream));
+    return MRT_OK;
+}
+
+int mrt_density_adjoint(mrt_ctx* c, const double* g_rho, void* lam) {
+    if (!c || !g_rho || !lam) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    HIPTRY(mrt::k_density_adjoint(c->prec, c->d_inst, (long long)c->nx * c->ny, g_rho, lam, c->stream));
+    return MRT_OK;
+}
+
+int mrt_init_adjoint(mrt_ctx* c, const void* lam0, const double* rho, const double* ux,
+                     const double* uy, const double* T, double* g_rho, double* g_ux, double* g_uy,
+                     double* g_T) {
+    if (!c || !lam0 || !rho || !ux || !uy || !T) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    HIPTRY(mrt::k_init_adjoint(c->prec, c->d_inst, (long long)c->nx * c->ny, lam0, rho, ux, uy, T,
+                               g_rho, g_ux, g_uy, g_T, c->stream));
+    return MRT_OK;
+}
+
+int mrt_init_buffer(mrt_ctx* c, const double* rho, const double* ux, const double* uy,
+                    const double* T, void* f) {
+    if (!c || !rho || !ux || !uy || !T || !f) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    HIPTRY(mrt::k_init(c->prec, c->d_inst, (long long)c->nx * c->ny, rho, ux, uy, T, f, c->stream));
+    return MRT_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batch
+
+struct mrt_batch {
+    int count = 0, prec = 0;
+    hipStream_t stream = nullptr;
+    std::vector<Inst> insts;
+    std::vector<long long> cells;
+    long long total_cells = 0, total_elems = 0, max_cells = 0;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    Inst* d_insts = nullptr;
+    Item* d_items = nullptr;
+    int nitems = 0, rows = 0, grid = 0;
+    double* d_stage = nullptr;
+    unsigned* d_health = nullptr;
+    std::map<int, hipGraphExec_t> graphs;   // n steps -> captured launches
+    std::string err;
+};
+
+namespace {
+
+int batch_items(mrt_batch* b, int rows) {
+    std::string& ctx_err = b->err;
+    std::vector<Item> items;
+    for (int i = 0; i < b->count; ++i) {
+        b->insts[i].item0 = int(items.size());
+        add_items(items, i, b->insts[i].nx, b->insts[i].ny, std::min(rows, b->insts[i].ny));
+    }
+    if (b->d_items) HIPTRY(hipFree(b->d_items));
+    b->d_items = nullptr;
+    HIPTRY(hipMalloc(&b->d_items, items.size() * sizeof(Item)));
+    HIPTRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    b->nitems = int(items.size());
+    b->rows = rows;
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+    return MRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int precision,
+                     void* stream) {
+    if (!out) return MRT_EINVAL;
+    *out = nullptr;
+    if (count < 1 || !desc || precision < 0 || precision > 2) return MRT_EINVAL;
+    mrt_batch* b = new mrt_batch();
+    std::string& ctx_err = b->err;
+    b->count = count;
+    b->prec = precision;
+    b->stream = static_cast<hipStream_t>(stream);
+    b->insts.resize(count);
+    b->cells.resize(count);
+    long long off = 0;
+    int maxny = 1;
+    for (int i = 0; i < count; ++i) {
+        const mrt_instance& d = desc[i];
+        if (d.nx < 1 || d.ny < 1 || !bc_ok(d.bc)) {
+            delete b;
+            return MRT_EINVAL;
+        }
+        Inst& I = b->insts[i];
+        I = Inst{};
+        I.nx = d.nx;
+        I.ny = d.ny;
+        I.pitch = int(pitch_for(d.nx));
+        I.plane = plane_for(d.nx, d.ny);
+        I.off = off;
+        std::string e;
+        if (fill_inst(I, d.nx, d.ny, d.bc, &d.params, e) != MRT_OK) {
+            delete b;
+            return MRT_EINVAL;
+        }
+        off += 16 * I.plane;
+        b->cells[i] = (long long)d.nx * d.ny;
+        b->total_cells += b->cells[i];
+        b->max_cells = std::max(b->max_cells, b->cells[i]);
+        maxny = std::max(maxny, d.ny);
+    }
+    b->total_elems = off;
+    const size_t bytes = size_t(off) * elem_size(precision);
+    auto fail = [&](int code) {
+        mrt_batch_destroy(b);
+        return code;
+    };
+    if (hipMalloc(&b->f[0], bytes) != hipSuccess || hipMalloc(&b->f[1], bytes) != hipSuccess ||
+        hipMalloc(&b->d_insts, sizeof(Inst) * count) != hipSuccess ||
+        hipMalloc(&b->d_stage, 4 * sizeof(double) * size_t(b->max_cells)) != hipSuccess ||
+        hipMalloc(&b->d_health, sizeof(unsigned)) != hipSuccess)
+        return fail(MRT_ENOMEM);
+    if (hipMemset(b->f[0], 0, bytes) != hipSuccess || hipMemset(b->f[1], 0, bytes) != hipSuccess ||
+        hipMemset(b->d_health, 0, sizeof(unsigned)) != hipSuccess)
+        return fail(MRT_EDEVICE);
+    if (batch_items(b, std::min(maxny, 64)) != MRT_OK) return fail(MRT_EDEVICE);
+    if (hipMemcpy(b->d_insts, b->insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(MRT_EDEVICE);
+    (void)ctx_err;
+    *out = b;
+    return MRT_OK;
+}
+
+int mrt_batch_set_fields(mrt_batch* b, int i, const double* rho, const double* ux,
+                         const double* uy, const double* T) {
+    if (!b || i < 0 || i >= b->count || !rho || !ux || !uy || !T) return MRT_EINVAL;
+    std::string& ctx_err = b->err;
+    const long long n = b->cells[i];
+    for (long long k = 0; k < n; ++k)
+        if (!(rho[k] > 0 && T[k] > 0)) {
+            b->err = "rho and T must be > 0";
+            return MRT_EINVAL;
+        }
+    double* s = b->d_stage;
+    const size_t by = sizeof(double) * size_t(n);
+    HIPTRY(hipMemcpyAsync(s, rho, by, hipMemcpyHostToDevice, b->stream));
+    HIPTRY(hipMemcpyAsync(s + n, ux, by, hipMemcpyHostToDevice, b->stream));
+    HIPTRY(hipMemcpyAsync(s + 2 * n, uy, by, hipMemcpyHostToDevice, b->stream));
+    HIPTRY(hipMemcpyAsync(s + 3 * n, T, by, hipMemcpyHostToDevice, b->stream));
+    HIPTRY(mrt::k_init(b->prec, b->d_insts + i, n, s, s + n, s + 2 * n, s + 3 * n, b->f[b->cur], b->stream));
+    HIPTRY(hipStreamSynchronize(b->stream));
+    return MRT_OK;
+}
+
+int mrt_batch_step(mrt_batch* b, int n) {
+    if (!b || n < 0) return MRT_EINVAL;
+    std::string& ctx_err = b->err;
+    if (n == 0) return MRT_OK;
+    // graph of n launches starting from buffer 0; a start from buffer 1 uses
+    // the key -n (the buffers alternate the other way)
+    const int key = b->cur == 0 ? n : -n;
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+        hipStream_t cap = nullptr;
+        HIPTRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        HIPTRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        int c = b->cur;
+        for (int k = 0; k < n; ++k) {
+            hipError_t e = mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[c], b->f[1 - c],
+                                       b->d_health, b->grid, cap);
+            if (e != hipSuccess) {
+                hipGraph_t g;
+                (void)hipStreamEndCapture(cap, &g);
+                (void)hipStreamDestroy(cap);
+                b->err = std::string("capture: ") + hipGetErrorString(e);
+                return MRT_EDEVICE;
+            }
+            c ^= 1;
+        }
+        hipGraph_t graph = nullptr;
+        HIPTRY(hipStreamEndCapture(cap, &graph));
+        hipGraphExec_t exec = nullptr;
+        HIPTRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        HIPTRY(hipGraphDestroy(graph));
+        HIPTRY(hipStreamDestroy(cap));
+        it = b->graphs.emplace(key, exec).first;
+    }
+    HIPTRY(hipGraphLaunch(it->second, b->stream));
+    if (n & 1) b->cur ^= 1;
+    return MRT_OK;
+}
+
+int mrt_batch_read_moments(mrt_batch* b, int i, double* rho, double* ux, double* uy, double* T) {
+    if (!b || i < 0 || i >= b->count) return MRT_EINVAL;
+    std::string& ctx_err = b->err;
+    const long long n = b->cells[i];
+    double* s = b->d_stage;
+    HIPTRY(mrt::k_moments(b->prec, b->d_insts + i, n, b->f[b->cur], s, s + n, s + 2 * n, s + 3 * n,
+                          b->d_health, b->stream));
+    double* outs[4] = {rho, ux, uy, T};
+    for (int k = 0; k < 4; ++k)
+        if (outs[k])
+            HIPTRY(hipMemcpyAsync(outs[k], s + k * n, sizeof(double) * size_t(n), hipMemcpyDeviceToHost, b->stream));
+    unsigned h = 0;
+    HIPTRY(hipMemcpyAsync(&h, b->d_health, sizeof h, hipMemcpyDeviceToHost, b->stream));
+    HIPTRY(hipStreamSynchronize(b->stream));
+    if (h) {
+        HIPTRY(hipMemsetAsync(b->d_health, 0, sizeof(unsigned), b->stream));
+        HIPTRY(hipStreamSynchronize(b->stream));
+        b->err = "non-finite value, rho <= 0 or T <= 0 detected";
+        return MRT_EUNSTABLE;
+    }
+    return MRT_OK;
+}
+
+int mrt_batch_get_populations(mrt_batch* b, int i, double* f) {
+    if (!b || i < 0 || i >= b->count || !f) return MRT_EINVAL;
+    std::string& ctx_err = b->err;
+    const long long n = b->cells[i];
+    double* tmp = nullptr;
+    HIPTRY(hipMallocAsync((void**)&tmp, sizeof(double) * 16 * size_t(n), b->stream));
+    HIPTRY(mrt::k_export(b->prec, b->d_insts + i, n, b->f[b->cur], tmp, b->stream));
+    HIPTRY(hipMemcpyAsync(f, tmp, sizeof(double) * 16 * size_t(n), hipMemcpyDeviceToHost, b->stream));
+    HIPTRY(hipFreeAsync(tmp, b->stream));
+    HIPTRY(hipStreamSynchronize(b->stream));
+    return MRT_OK;
+}
+
+int mrt_batch_set_tile(mrt_batch* b, int rows, int grid) {
+    if (!b || rows < 1 || grid < 0) return MRT_EINVAL;
+    const int rc = batch_items(b, rows);
+    if (rc != MRT_OK) return rc;
+    std::string& ctx_err = b->err;
+    HIPTRY(hipMemcpy(b->d_insts, b->insts.data(), sizeof(Inst) * b->count, hipMemcpyHostToDevice));
+    b->grid = grid;
+    return MRT_OK;
+}
+
+int mrt_batch_get_tile(const mrt_batch* b, int* rows, int* grid) {
+    if (!b) return MRT_EINVAL;
+    if (rows) *rows = b->rows;
+    if (grid) *grid = b->grid;
+    return MRT_OK;
+}
+
+int mrt_batch_autotune(mrt_batch* b, int steps) {
+    if (!b) return MRT_EINVAL;
+    std::string& ctx_err = b->err;
+    if (steps < 1) steps = 8;
+    const size_t bytes = size_t(b->total_elems) * elem_size(b->prec);
+    void* save = nullptr;
+    HIPTRY(hipMalloc(&save, bytes));
+    HIPTRY(hipMemcpyAsync(save, b->f[b->cur], bytes, hipMemcpyDeviceToDevice, b->stream));
+    hipEvent_t e0, e1;
+    HIPTRY(hipEventCreate(&e0));
+    HIPTRY(hipEventCreate(&e1));
+    int dev = 0, cus = 0;
+    HIPTRY(hipGetDevice(&dev));
+    HIPTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int maxny = 1;
+    for (const auto& I : b->insts) maxny = std::max(maxny, I.ny);
+    const int row_opts[] = {1, 2, 4, 8, 16, 32, 64};
+    const int grid_mult[] = {0, 2, 4, 8};
+    float best = 1e30f;
+    int best_rows = b->rows, best_grid = b->grid;
+    const int cur0 = b->cur;
+    for (int r : row_opts) {
+        if (r > maxny) break;
+        for (int gm : grid_mult) {
+            if (mrt_batch_set_tile(b, r, gm * cus) != MRT_OK) return MRT_EDEVICE;
+            if (gm != 0 && gm * cus * 4 >= b->nitems) continue;
+            mrt_batch_step(b, steps);    // capture + warm-up
+            HIPTRY(hipEventRecord(e0, b->stream));
+            mrt_batch_step(b, steps);
+            HIPTRY(hipEventRecord(e1, b->stream));
+            HIPTRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                best_rows = r;
+                best_grid = gm * cus;
+            }
+            b->cur = cur0;
+            HIPTRY(hipMemcpyAsync(b->f[b->cur], save, bytes, hipMemcpyDeviceToDevice, b->stream));
+        }
+    }
+    HIPTRY(hipStreamSynchronize(b->stream));
+    HIPTRY(hipEventDestroy(e0));
+    HIPTRY(hipEventDestroy(e1));
+    HIPTRY(hipFree(save));
+    HIPTRY(hipMemsetAsync(b->d_health, 0, sizeof(unsigned), b->stream));
+    const int rc = mrt_batch_set_tile(b, best_rows, best_grid);
+    HIPTRY(hipStreamSynchronize(b->stream));
+    return rc;
+}
+
+long long mrt_batch_cells(const mrt_batch* b) { return b ? b->total_cells : 0; }
+
+void mrt_batch_destroy(mrt_batch* b) {
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    if (b->f[0]) (void)hipFree(b->f[0]);
+    if (b->f[1]) (void)hipFree(b->f[1]);
+    if (b->d_insts) (void)hipFree(b->d_insts);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->d_stage) (void)hipFree(b->d_stage);
+    if (b->d_health) (void)hipFree(b->d_health);
+    delete b;
+}
+
+const char* mrt_batch_last_error(const mrt_batch* b) { return b ? b->err.c_str() : "NULL batch"; }
+
+// --------------------------------------------------------- host utilities
+// The same templated transform code the kernels run, evaluated on the host
+// in FP64.  Used by the library for boundary equilibria and exported for
+// CPU-side checks of the factored transforms.
+
+int mrt_host_transform(int which, const double* in, double* out) {
+    if (!in || !out) return MRT_EINVAL;
+    switch (which) {
+        case 0: mrt::pops_to_moments(in, out); return MRT_OK;
+        case 1: mrt::moments_to_pops(in, out); return MRT_OK;
+        case 2: mrt::moments_T(in, out); return MRT_OK;
+        case 3: mrt::inverse_T(in, out); return MRT_OK;
+        default: return MRT_EINVAL;
+    }
+}
+
+int mrt_host_equilibrium(double gamma, double rho, double ux, double uy, double T, double* f) {
+    if (!f || !(gamma > 1.0)) return MRT_EINVAL;
+    mrt::equilibrium_pops<double>(rho, ux, uy, T, 2.0 / (gamma - 1.0), f);
+    return MRT_OK;
+}
+
+int mrt_host_collision(double gamma, const double* s, double dt, const double* f, double* out) {
+    if (!s || !f || !out || !(gamma > 1.0)) return MRT_EINVAL;
+    double sdt[16];
+    for (int k = 0; k < 16; ++k) sdt[k] = s[k] * dt;
+    double rho, P;
+    mrt::collision_dt<double>(f, 2.0 / (gamma - 1.0), sdt, out, rho, P);
+    return MRT_OK;
+}
+
+int mrt_host_cell_adjoint(double gamma, const double* s, double dt, const double* f,
+                          const double* lam, double* coll, double* dsk) {
+    if (!s || !f || !lam || !coll || !dsk || !(gamma > 1.0)) return MRT_EINVAL;
+    double sdt[16];
+    for (int k = 0; k < 16; ++k) sdt[k] = k < 4 ? 0.0 : s[k] * dt;
+    mrt::cell_adjoint<double>(f, lam, 2.0 / (gamma - 1.0), sdt, dt, coll, dsk);
+    return MRT_OK;
+}
+
+}  // extern "C"

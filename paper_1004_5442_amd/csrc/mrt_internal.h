@@ -1,0 +1,52 @@
+// mrt_internal.h -- data shared by the host library and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "mrt_transform.h"
+
+namespace mrt {
+
+enum { XLO = 0, XHI = 1, YLO = 2, YHI = 3 };
+enum { BC_PERIODIC = 0, BC_EQ = 1, BC_OUTFLOW = 2, BC_REFLECT = 3 };
+
+// One grid (instance) as the kernels see it.  Read by every lane of a wave
+// at the same address, so it lives in scalar registers / the scalar cache.
+struct Inst {
+    long long off;      // element offset of population plane 0 in the buffers
+    long long plane;    // elements between population planes (= ny * pitch)
+    int nx, ny, pitch;
+    int item0;          // first work item of this instance (partial-sum rows)
+    int bc[4];
+    double b;           // dof: gamma = (b + 2)/b
+    double dt;
+    double sdt[16];     // s_k dt; entries 0..3 unused (collision invariants)
+    // Lax-Wendroff weights per axis (0: x, 1: y) and shell for a velocity
+    // component +c, c = |v_a| dt / dx_a >= 0:
+    //   [0] c^2/2 - c/2  weight of the downstream neighbour (x + 1)
+    //   [1] c^2/2 + c/2  weight of the upstream neighbour (x - 1)
+    // (for a component -c the two swap); they sum to c^2.
+    double lw[2][4][2];
+    float lwf[2][4][2];
+    double ghost[4][16];   // f^eq of each MRT_BC_EQ side
+};
+
+// Work item: one wave advances 64 columns [x0, x0 + 64) of rows [y0, y1) of
+// instance `inst`.
+struct Item {
+    int inst, x0, y0, y1;
+};
+
+// velocity component signs per population: +1, -1 or 0
+MRT_HD int sgn_x(int i) {
+    const int r = i & 3;
+    if (i < 8) return r == 0 ? 1 : (r == 2 ? -1 : 0);
+    return (r == 0 || r == 3) ? 1 : -1;
+}
+MRT_HD int sgn_y(int i) {
+    const int r = i & 3;
+    if (i < 8) return r == 1 ? 1 : (r == 3 ? -1 : 0);
+    return (r == 0 || r == 1) ? 1 : -1;
+}
+
+}  // namespace mrt
