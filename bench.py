@@ -95,6 +95,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -105,10 +108,17 @@ def main():
 
     from paper_1004_5442_amd import workloads as W
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     n = 4096
     head = W.shock_bubble(n=n)
     prec = "fp32_eq64"
-    r = time_solver(head, prec, args.steps, args.warmup)
+    r = time_solver(head, prec, args.steps, args.warmup, autotune=not args.no_autotune)
     r["steps"] = args.steps
     out = {
         "metric": "MLUPS (million lattice-site updates per second) of the MRT FD-LB step",

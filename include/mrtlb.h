@@ -23,8 +23,10 @@
  *  - Grid fields are row-major ny x nx arrays (x fastest), cell-centred:
  *    cell (i, j) sits at ((i + 1/2) dx, (j + 1/2) dy).
  *  - Populations are stored structure-of-arrays: plane i (0..15) holds f_i for
- *    every cell, f[i * plane + j * pitch + x]; pitch >= nx and
- *    plane >= ny * pitch are chosen by the library (mrt_get_layout).  Velocity order: shell 1 (speed 1) and shell 2
+ *    every cell, f[i * plane + origin + j * pitch + x], with one ghost cell on
+ *    each side (-1 <= x <= nx, -1 <= j <= ny) that the library fills from the
+ *    boundary conditions before each step; pitch (a multiple of 64, >= nx + 2),
+ *    plane and origin come from mrt_get_layout.  Velocity order: shell 1 (speed 1) and shell 2
  *    (speed 6) as (+x, +y, -x, -y); shell 3 (sqrt(2)(+-1,+-1)) and shell 4
  *    ((3/sqrt 2)(+-1,+-1)) as (++, -+, --, +-).
  *  - Device pointers are plain HIP device addresses; host pointers are
@@ -72,7 +74,8 @@ typedef struct mrt_params {
                               Eqs. 12b-12d) and s[6] must equal s[5]              */
     double s[16];          /* relaxation rates s_1..s_16 (s[k-1] = s_k).  s_1..4
                               multiply collision invariants and are ignored;
-                              s_5..16 must lie in [0, 1/dt] (text after Eq. 12d) */
+                              s_5..16 must lie in [0, 1/dt] (text after Eq. 12d;
+                              s dt up to 1 + 1e-6 is accepted)                  */
     double dt, dx, dy;     /* time step and cell sizes, all > 0                   */
     double eta0;           /* eta on shell 1; the paper fixes 5/2 and so does this
                               library (any other value: MRT_EINVAL)              */
@@ -97,8 +100,9 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
 /* Bytes of one population buffer for a grid (16 planes, padded pitch). */
 long long mrt_population_bytes(int nx, int ny, int precision);
 
-/* Row pitch (elements) and plane stride (elements) of the population layout. */
-int mrt_get_layout(const mrt_ctx* ctx, long long* pitch, long long* plane);
+/* Row pitch, plane stride and offset of cell (0, 0) in a plane (elements) of
+ * the population layout.  Any output may be NULL. */
+int mrt_get_layout(const mrt_ctx* ctx, long long* pitch, long long* plane, long long* origin);
 
 /* Validate and copy parameters (see mrt_params).  Computes the ghost
  * equilibria of MRT_BC_EQ sides.  Errors: MRT_EINVAL. */
@@ -161,13 +165,15 @@ const char* mrt_last_error(const mrt_ctx* ctx);
  *            dF/ds_k = -dt Minv[:,k] (fhat_k - fhat^eq_k)      (derived from Eq. 3)
  * lam_next, f_n, lam_n: device buffers in the context's storage precision and
  * padded layout (as mrt_current_buffer).  ds: 16 device doubles, accumulated
- * (the caller zeroes it).  Asynchronous.  lam_n must not alias lam_next. */
+ * (the caller zeroes it).  Asynchronous.  lam_n must not alias lam_next; the
+ * ghost ring of lam_next is refilled (periodic wrap). */
 int mrt_adjoint_step(mrt_ctx* ctx, const void* lam_next, const void* f_n, void* lam_n,
                      double* ds);
 
 /* One forward step between explicit device buffers (storage precision,
  * padded layout), without touching the context's own buffers: used to
- * recompute states from checkpoints.  Asynchronous. */
+ * recompute states from checkpoints.  The ghost ring of f_in is refilled
+ * (its cells are not changed).  Asynchronous. */
 int mrt_step_buffers(mrt_ctx* ctx, const void* f_in, void* f_out);
 
 /* Density of an explicit population buffer: rho[j*nx+x] = sum_i f_i (device

@@ -1,0 +1,86 @@
+"""Gradients of a final-state density through the scheme: hand-written adjoint
+kernels behind ``torch.autograd.Function``, with sqrt(N) checkpointing.
+
+Forward:  f^0 = Minv fhat^eq(rho0, u0 = 0, T0);  f^{n+1} = F(f^n; s), n < N;
+          rho^N = sum_i f_i^N.
+Backward: lam^N = g_rho (every population), then per step, newest first,
+          lam^n = (dF/df^n)^T lam^{n+1} and ds += lam^{n+1} . dF/ds
+          (``mrt_adjoint_step``), and finally the adjoint of the
+          initialisation gives (d/d rho0, d/d T0) (``mrt_init_adjoint``).
+The states f^n needed by the backward pass are not all kept: every K-th
+state (K ~ sqrt(N)) is stored in the forward pass, and each segment of K
+states is recomputed from its checkpoint just before its adjoint steps, so
+memory is O(sqrt(N)) states for one extra forward pass.  Periodic grids only.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import torch
+
+from .solver import Solver
+
+
+class DensityMap(torch.autograd.Function):
+    """rho^N = Phi(rho0, T0, s) for a periodic grid (u0 = 0)."""
+
+    @staticmethod
+    def forward(ctx, rho0: torch.Tensor, T0: torch.Tensor, s: torch.Tensor, solver: Solver,
+                gamma: float, dt: float, dx: float, dy: float, nsteps: int,
+                segment: Optional[int] = None):
+        sv = s.detach().to("cpu", torch.float64)
+        solver.set_params(gamma, sv.tolist(), dt, dx, dy, 0.0)
+        K = int(segment or max(1, math.ceil(math.sqrt(nsteps))))
+        dev = rho0.device
+        rho0d = rho0.detach().to(dev, torch.float64).contiguous()
+        T0d = T0.detach().to(dev, torch.float64).contiguous()
+        zero = torch.zeros_like(rho0d)
+        a, b = solver.empty_state(), solver.empty_state()
+        solver.init_buffer(rho0d, zero, zero, T0d, a)
+        checkpoints = []
+        for n in range(nsteps):
+            if n % K == 0:
+                checkpoints.append(a.clone())
+            solver.step_buffers(a, b)
+            a, b = b, a
+        rhoN = torch.empty_like(rho0d)
+        solver.density(a, rhoN)
+        ctx.solver, ctx.K, ctx.nsteps = solver, K, nsteps
+        ctx.checkpoints = checkpoints
+        ctx.save_for_backward(rho0d, T0d)
+        ctx.s_meta = (s.device, s.dtype)
+        return rhoN
+
+    @staticmethod
+    def backward(ctx, g_rhoN: torch.Tensor):
+        solver, K, N = ctx.solver, ctx.K, ctx.nsteps
+        rho0d, T0d = ctx.saved_tensors
+        lam, lam2 = solver.empty_state(), solver.empty_state()
+        solver.density_adjoint(g_rhoN.detach().to(torch.float64).contiguous(), lam)
+        ds = torch.zeros(16, dtype=torch.float64, device=rho0d.device)
+        nseg = len(ctx.checkpoints)
+        for seg in range(nseg - 1, -1, -1):
+            start = seg * K
+            stop = min(N, start + K)
+            # recompute f^start .. f^{stop-1}
+            states = [ctx.checkpoints[seg]]
+            for n in range(start, stop - 1):
+                nxt = solver.empty_state()
+                solver.step_buffers(states[-1], nxt)
+                states.append(nxt)
+            for n in range(stop - 1, start - 1, -1):
+                solver.adjoint_step(lam, states[n - start], lam2, ds)
+                lam, lam2 = lam2, lam
+            del states
+        zero = torch.zeros_like(rho0d)
+        g_rho, g_T = torch.empty_like(rho0d), torch.empty_like(rho0d)
+        solver.init_adjoint(lam, rho0d, zero, zero, T0d, g_rho=g_rho, g_T=g_T)
+        sdev, sdt = ctx.s_meta
+        ctx.checkpoints = None
+        return g_rho, g_T, ds.to(sdev, sdt), None, None, None, None, None, None, None
+
+
+def density_after(rho0, T0, s, solver: Solver, gamma, dt, dx, dy, nsteps, segment=None):
+    """Differentiable rho^N (see DensityMap)."""
+    return DensityMap.apply(rho0, T0, s, solver, gamma, dt, dx, dy, nsteps, segment)

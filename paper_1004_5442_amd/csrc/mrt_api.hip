@@ -19,6 +19,8 @@
 #include "../../include/mrtlb.h"
 
 namespace mrt {
+hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, bool force_periodic,
+                   hipStream_t st);
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                   void* fout, unsigned* health, int grid, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
@@ -47,11 +49,15 @@ namespace {
 
 size_t elem_size(int prec) { return prec == MRT_FP64 ? 8 : 4; }
 
-long long pitch_for(int nx) { return ((long long)nx + 63) / 64 * 64; }
-
-// Plane stride: rows * pitch plus an odd number of 64-element blocks, so the
-// 16 planes of one row do not sit at a large power-of-two distance apart.
-long long plane_for(int nx, int ny) { return (long long)ny * pitch_for(nx) + 5 * 64; }
+// Population layout per plane: rows -1..ny of `pitch` elements (pitch a
+// multiple of 64 >= nx + 2, so every row starts 256-byte aligned and the
+// ghost columns x = -1 / x = nx fit in the row padding), preceded by one
+// 64-element block; cell (0, 0) sits at `origin`.  The plane stride adds an
+// odd number of 64-element blocks so the 16 planes of one row are not a large
+// power of two apart.
+long long pitch_for(int nx) { return ((long long)nx + 2 + 63) / 64 * 64; }
+long long origin_for(int nx) { return pitch_for(nx) + 64; }
+long long plane_for(int nx, int ny) { return (long long)(ny + 2) * pitch_for(nx) + 128 + 5 * 64; }
 
 bool bc_ok(const int bc[4]) {
     for (int k = 0; k < 4; ++k)
@@ -81,7 +87,9 @@ int fill_inst(Inst& I, int nx, int ny, const int bc[4], const mrt_params* p, std
     }
     for (int k = 4; k < 16; ++k) {
         const double sd = s[k] * p->dt;
-        if (!(sd >= 0.0 && sd <= 1.0 + 1e-12)) {
+        // [0, 1/dt] (text after Eq. 12d), with 1e-6 of slack for rates set to
+        // exactly 1/dt and then perturbed (finite-difference checks)
+        if (!(sd >= 0.0 && sd <= 1.0 + 1e-6)) {
             char buf[96];
             std::snprintf(buf, sizeof buf, "s_%d * dt = %g outside [0, 1]", k + 1, sd);
             err = buf;
@@ -89,6 +97,7 @@ int fill_inst(Inst& I, int nx, int ny, const int bc[4], const mrt_params* p, std
         }
     }
     I.b = 2.0 / (p->gamma - 1.0);
+    I.binv = 1.0 / I.b;
     I.dt = p->dt;
     for (int k = 0; k < 16; ++k) I.sdt[k] = k < 4 ? 0.0 : s[k] * p->dt;
     const double h[2] = {p->dx, p->dy};
@@ -146,7 +155,7 @@ struct mrt_ctx {
     void* f[2] = {nullptr, nullptr};
     bool own_f = false;
     int cur = 0;
-    long long pitch = 0, plane = 0;
+    long long pitch = 0, plane = 0, origin = 0;
     Inst inst{};
     Inst* d_inst = nullptr;
     Item* d_items = nullptr;
@@ -218,6 +227,7 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     c->stream = static_cast<hipStream_t>(stream);
     c->pitch = pitch_for(nx);
     c->plane = plane_for(nx, ny);
+    c->origin = origin_for(nx);
     const size_t bytes = size_t(mrt_population_bytes(nx, ny, precision));
     auto fail = [&](int code) {
         mrt_destroy(c);
@@ -246,6 +256,7 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     c->inst.nx = nx;
     c->inst.ny = ny;
     c->inst.pitch = int(c->pitch);
+    c->inst.origin = int(c->origin);
     c->inst.item0 = 0;
     for (int k = 0; k < 4; ++k) c->inst.bc[k] = bc[k];
     if (build_items(c, default_rows(nx, ny)) != MRT_OK) return fail(MRT_EDEVICE);
@@ -254,10 +265,11 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     return MRT_OK;
 }
 
-int mrt_get_layout(const mrt_ctx* c, long long* pitch, long long* plane) {
+int mrt_get_layout(const mrt_ctx* c, long long* pitch, long long* plane, long long* origin) {
     if (!c) return MRT_EINVAL;
     if (pitch) *pitch = c->pitch;
     if (plane) *plane = c->plane;
+    if (origin) *origin = c->origin;
     return MRT_OK;
 }
 
@@ -304,7 +316,9 @@ int mrt_step(mrt_ctx* c, int n) {
     std::string& ctx_err = c->err;
     if (n < 0) return ctx_fail(c, MRT_EINVAL, "n < 0");
     if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
+    const int perim = 2 * (c->nx + c->ny);
     for (int k = 0; k < n; ++k) {
+        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[c->cur], false, c->stream));
         HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[c->cur], c->f[1 - c->cur],
                            c->d_health, c->grid, c->stream));
         c->cur ^= 1;
@@ -317,6 +331,8 @@ int mrt_step_buffers(mrt_ctx* c, const void* fin, void* fout) {
     std::string& ctx_err = c->err;
     if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
     if (!fin || !fout || fin == fout) return ctx_fail(c, MRT_EINVAL, "need two distinct buffers");
+    HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(fin), false,
+                        c->stream));
     HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, fin, fout, c->d_health, c->grid,
                        c->stream));
     return MRT_OK;
@@ -491,6 +507,8 @@ int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* la
     if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
     if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
         return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
+    HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(lam_next),
+                        true, c->stream));
     HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items, c->nitems, lam_next, f_n, lam_n,
                           c->d_partial, ds, c->stream));
     return MRT_OK;
@@ -542,6 +560,7 @@ struct mrt_batch {
     std::vector<Inst> insts;
     std::vector<long long> cells;
     long long total_cells = 0, total_elems = 0, max_cells = 0;
+    int max_perim = 0;
     void* f[2] = {nullptr, nullptr};
     int cur = 0;
     Inst* d_insts = nullptr;
@@ -602,7 +621,9 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
         I.nx = d.nx;
         I.ny = d.ny;
         I.pitch = int(pitch_for(d.nx));
+        I.origin = int(origin_for(d.nx));
         I.plane = plane_for(d.nx, d.ny);
+        b->max_perim = std::max(b->max_perim, 2 * (d.nx + d.ny));
         I.off = off;
         std::string e;
         if (fill_inst(I, d.nx, d.ny, d.bc, &d.params, e) != MRT_OK) {
@@ -672,8 +693,10 @@ int mrt_batch_step(mrt_batch* b, int n) {
         HIPTRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         int c = b->cur;
         for (int k = 0; k < n; ++k) {
-            hipError_t e = mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[c], b->f[1 - c],
-                                       b->d_health, b->grid, cap);
+            hipError_t e = mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[c], false, cap);
+            if (e == hipSuccess)
+                e = mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[c], b->f[1 - c],
+                                b->d_health, b->grid, cap);
             if (e != hipSuccess) {
                 hipGraph_t g;
                 (void)hipStreamEndCapture(cap, &g);

@@ -84,7 +84,7 @@ MRT_HD void cell_adjoint(const C f[16], const C lam[16], C b, const double* sdt,
     Dual4<C> q[4], eqd[16];
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] = Dual4<C>::var(m[k], k);
-    equilibrium_moments(q[0], q[1], q[2], q[3], Dual4<C>(double(b)), eqd);
+    equilibrium_moments(q[0], q[1], q[2], q[3], Dual4<C>(double(b)), Dual4<C>(1.0 / double(b)), eqd);
     C zeta[16];
     C g[4] = {C(0), C(0), C(0), C(0)};
 #pragma unroll

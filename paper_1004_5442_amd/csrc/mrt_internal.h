@@ -14,11 +14,17 @@ enum { BC_PERIODIC = 0, BC_EQ = 1, BC_OUTFLOW = 2, BC_REFLECT = 3 };
 // at the same address, so it lives in scalar registers / the scalar cache.
 struct Inst {
     long long off;      // element offset of population plane 0 in the buffers
-    long long plane;    // elements between population planes (= ny * pitch)
-    int nx, ny, pitch;
+    long long plane;    // elements between population planes
+    int nx, ny, pitch;  // pitch >= nx + 2 and a multiple of 64
+    int origin;         // offset of cell (0, 0) in a plane; cell (x, y) of plane i
+                        // is at off + i * plane + origin + y * pitch + x for
+                        // -1 <= x <= nx, -1 <= y <= ny (x or y outside [0, n):
+                        // the ghost ring)
     int item0;          // first work item of this instance (partial-sum rows)
+    int pad0;
     int bc[4];
     double b;           // dof: gamma = (b + 2)/b
+    double binv;        // 1/b
     double dt;
     double sdt[16];     // s_k dt; entries 0..3 unused (collision invariants)
     // Lax-Wendroff weights per axis (0: x, 1: y) and shell for a velocity

@@ -84,12 +84,12 @@ __device__ __forceinline__ void conserved_compensated(const float f[16], float q
     for (int m = 0; m < 4; ++m) q[m] = s[m] + c[m];
 }
 
-// dt * C for one cell in precision C (see collision_dt); COMP replaces the
-// conserved moments by compensated FP32 sums.
+// dt * C for one cell in precision C (see collision_dt), converted to the
+// storage type; COMP replaces the conserved moments by compensated FP32 sums.
 template <typename C, bool COMP, typename S>
-__device__ __forceinline__ void cell_collision(const S fs[16], C b, const double* sdt, C out[16],
-                                               C& rho, C& P) {
-    C f[16], m[16], eq[16], dm[16];
+__device__ __forceinline__ void cell_collision(const S fs[16], C b, C binv, const double* sdt,
+                                               S out[16], C& rho, C& P) {
+    C f[16], m[16], eq[16], dm[16], o[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) f[i] = C(fs[i]);
     pops_to_moments(f, m);
@@ -100,44 +100,13 @@ __device__ __forceinline__ void cell_collision(const S fs[16], C b, const double
         for (int k = 0; k < 4; ++k) m[k] = q[k];
     }
     rho = m[0];
-    P = equilibrium_moments(m[0], m[1], m[2], m[3], b, eq);
+    P = equilibrium_moments(m[0], m[1], m[2], m[3], b, binv, eq);
     dm[0] = dm[1] = dm[2] = dm[3] = C(0);
 #pragma unroll
     for (int k = 4; k < 16; ++k) dm[k] = C(sdt[k]) * (m[k] - eq[k]);
-    moments_to_pops(dm, out);
-}
-
-// Equilibrium of the cell's own state with one velocity component reversed
-// (reflecting wall): normal_x selects the x component.
-template <typename C, typename S>
-__device__ __forceinline__ void reflected_eq(const S fs[16], C b, bool normal_x, S g[16]) {
-    C f[16], m[16], eq[16], out[16];
+    moments_to_pops(dm, o);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) f[i] = C(fs[i]);
-    pops_to_moments(f, m);
-    const C jx = normal_x ? -m[1] : m[1];
-    const C jy = normal_x ? m[2] : -m[2];
-    equilibrium_moments(m[0], jx, jy, m[3], b, eq);
-    moments_to_pops(eq, out);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) g[i] = S(out[i]);
-}
-
-// Ghost row beyond side (YLO/YHI) for a non-periodic y boundary; r is the
-// adjacent interior row (all 16 populations).
-template <typename S, typename C>
-__device__ __forceinline__ void ghost_row(const Inst* __restrict__ P, int side, const S r[16],
-                                          S g[16]) {
-    const int kind = P->bc[side];
-    if (kind == BC_EQ) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[side][i]);
-    } else if (kind == BC_REFLECT) {
-        reflected_eq<C, S>(r, C(P->b), false, g);
-    } else {   // outflow (periodic rows are loaded by the caller)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) g[i] = r[i];
-    }
+    for (int i = 0; i < 16; ++i) out[i] = S(o[i]);
 }
 
 template <typename S>
@@ -151,159 +120,151 @@ struct Weights<double> {
     __device__ static double get(const Inst* P, int ax, int k, int j) { return P->lw[ax][k][j]; }
 };
 
+// ------------------------------------------------------------------ ghosts
+
+// Fill the ghost ring of one instance (x = -1 and x = nx for 0 <= y < ny;
+// y = -1 and y = ny for 0 <= x < nx) from the current populations:
+// periodic -> the wrapped cell, MRT_BC_EQ -> the side's equilibrium,
+// outflow -> the adjacent cell, reflecting -> the equilibrium of the
+// adjacent cell with its normal velocity reversed.  Corners are never read.
+template <typename S, typename C>
+__global__ __launch_bounds__(256) void ghost_kernel(const Inst* __restrict__ insts,
+                                                    S* __restrict__ f, int force_periodic) {
+    const Inst* __restrict__ P = insts + blockIdx.y;
+    const int nx = P->nx, ny = P->ny;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 2 * (nx + ny)) return;
+    int side, gx, gy, ix, iy, px, py;
+    if (t < ny) {
+        side = XLO; gx = -1; gy = t; ix = 0; iy = t; px = nx - 1; py = t;
+    } else if (t < 2 * ny) {
+        side = XHI; gx = nx; gy = t - ny; ix = nx - 1; iy = gy; px = 0; py = gy;
+    } else if (t < 2 * ny + nx) {
+        side = YLO; gx = t - 2 * ny; gy = -1; ix = gx; iy = 0; px = gx; py = ny - 1;
+    } else {
+        side = YHI; gx = t - 2 * ny - nx; gy = ny; ix = gx; iy = ny - 1; px = gx; py = 0;
+    }
+    const int kind = force_periodic ? int(BC_PERIODIC) : P->bc[side];
+    S* __restrict__ base = f + P->off + P->origin;
+    const long long plane = P->plane;
+    const long long go = (long long)gy * P->pitch + gx;
+    S g[16];
+    if (kind == BC_EQ) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[side][i]);
+    } else {
+        const bool per = kind == BC_PERIODIC;
+        const long long so = (long long)(per ? py : iy) * P->pitch + (per ? px : ix);
+        S c[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) c[i] = base[i * plane + so];
+        if (kind == BC_REFLECT) {
+            C fc[16], m[16], eq[16], out[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) fc[i] = C(c[i]);
+            pops_to_moments(fc, m);
+            const bool nxs = side == XLO || side == XHI;
+            equilibrium_moments(m[0], nxs ? -m[1] : m[1], nxs ? m[2] : -m[2], m[3], C(P->b),
+                                C(P->binv), eq);
+            moments_to_pops(eq, out);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) g[i] = S(out[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) g[i] = c[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) base[i * plane + go] = g[i];
+}
+
 // ------------------------------------------------------------------- step
 
-// Advance one work item: columns [x0, x0+64) of rows [y0, y1).
+// Advance one work item: columns [x0, x0+64) of rows [y0, y1) of one
+// instance.  The ghost ring holds every out-of-grid neighbour, so all
+// neighbours are plain loads: rows y-1 / y+1 from the register window,
+// columns x-1 / x+1 from the adjacent lanes (DPP wavefront shifts) and, on
+// lanes 0 and 63, from one halo load.  Lanes past the last column load the
+// ghost column / padding (in bounds: the pitch covers x0 + 64) and store
+// nothing.
 template <typename S, typename C, bool COMP>
 __device__ __forceinline__ void step_item(const Inst* __restrict__ P, int x0, int y0, int y1,
                                           const S* __restrict__ fin, S* __restrict__ fout,
                                           unsigned* __restrict__ health) {
     const int lane = lane_id();
-    const int nx = P->nx, ny = P->ny, pitch = P->pitch;
+    const unsigned pitch = unsigned(P->pitch);
     const long long plane = P->plane;
     const S* __restrict__ fi = fin + P->off;
     S* __restrict__ fo = fout + P->off;
     const int x = x0 + lane;
-    const bool act = x < nx;
-    const int xc = act ? x : nx - 1;
-    const int bxl = P->bc[XLO], bxh = P->bc[XHI], byl = P->bc[YLO], byh = P->bc[YHI];
-    const bool per_x = bxl == BC_PERIODIC;
-    const bool per_y = byl == BC_PERIODIC;
-    const C b = C(P->b);
+    const bool act = x < P->nx;
+    const C b = C(P->b), binv = C(P->binv);
+    // uniform plane base + 32-bit lane offset (global_load with saddr)
+    auto ld = [&](int i, unsigned off) -> S { return (fi + (long long)i * plane)[off]; };
+    const unsigned hoff = (lane == 0) ? unsigned(-1) : 1u;   // halo column relative to x
+    const bool hload = (lane == 0 || lane == 63);
+    const unsigned o_start = unsigned(P->origin) + unsigned(y0) * pitch + unsigned(x);
 
-    // halo column: lane 0 loads its west neighbour, lane 63 and the last
-    // column load their east neighbour (wrapped on a periodic axis)
-    int hx = (lane == 0) ? x - 1 : x + 1;
-    if (per_x) hx = hx < 0 ? hx + nx : (hx >= nx ? hx - nx : hx);
-    const bool hload = (lane == 0 || lane == 63 || x == nx - 1) && hx >= 0 && hx < nx;
-    const bool first_tile = x0 == 0;
-    const bool last_tile = x0 + 64 >= nx;
-    const bool lone_last = x0 == nx - 1;     // lane 0 is also the last column
-
-    auto at = [&](int i, int yy, int xx) -> long long {
-        return (long long)i * plane + (long long)yy * pitch + xx;
-    };
-
-    S r0[16], rm[16], rp[16];
+    auto body = [&](const S (&rm)[16], const S (&r0)[16], const S (&rp)[16], S (&rn)[16],
+                    int y, unsigned o) {
+        if (y + 1 < y1) {
 #pragma unroll
-    for (int i = 0; i < 16; ++i) r0[i] = fi[at(i, y0, xc)];
-    if (y0 > 0 || per_y) {
-        const int yy = y0 > 0 ? y0 - 1 : ny - 1;
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (moves_y(i)) rm[i] = fi[at(i, yy, xc)];
-    } else {
-        ghost_row<S, C>(P, YLO, r0, rm);
-    }
-    if (y0 + 1 < ny || per_y) {
-        const int yy = y0 + 1 < ny ? y0 + 1 : y0 + 1 - ny;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) rp[i] = fi[at(i, yy, xc)];
-    } else {
-        ghost_row<S, C>(P, YHI, r0, rp);
-    }
-
-    for (int y = y0; y < y1; ++y) {
-        const bool more = y + 1 < y1;
-        const bool next_real = (y + 2 < ny) || per_y;
-        S rn[16];
-        if (more && next_real) {
-            const int yy = y + 2 < ny ? y + 2 : y + 2 - ny;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) rn[i] = fi[at(i, yy, xc)];
+            for (int i = 0; i < 16; ++i) rn[i] = ld(i, o + 2 * pitch);
         }
-
-        // x neighbours of the x-moving populations
-        S h[16], W[16], E[16];
+        S h[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) h[i] = S(0);
         if (hload) {
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                if (moves_x(i)) h[i] = fi[at(i, y, hx)];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) h[i] = S(0);
+                if (moves_x(i)) h[i] = ld(i, o + hoff);
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (!moves_x(i)) continue;
-            W[i] = from_left(r0[i], h[i]);
-            E[i] = from_right(r0[i], h[i]);
-            if (x == nx - 1 && lane != 0 && lane != 63) E[i] = h[i];
-        }
-        if (lone_last && per_x) {          // lane 0 is column nx-1: east is column 0
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (moves_x(i) && lane == 0) E[i] = nx == 1 ? r0[i] : fi[at(i, y, 0)];
-        }
-        if (first_tile && !per_x) {
-            S g[16];
-            if (bxl == BC_EQ) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[XLO][i]);
-            } else if (bxl == BC_REFLECT) {
-                reflected_eq<C, S>(r0, b, true, g);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) g[i] = r0[i];
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (moves_x(i) && x == 0) W[i] = g[i];
-        }
-        if (last_tile && !per_x) {
-            S g[16];
-            if (bxh == BC_EQ) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[XHI][i]);
-            } else if (bxh == BC_REFLECT) {
-                reflected_eq<C, S>(r0, b, true, g);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) g[i] = r0[i];
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (moves_x(i) && x == nx - 1) E[i] = g[i];
-        }
-
-        // collision in moment space
-        C cdt[16], rho, Pp;
-        cell_collision<C, COMP>(r0, b, P->sdt, cdt, rho, Pp);
+        S cdt[16];
+        C rho, Pp;
+        cell_collision<C, COMP>(r0, b, binv, P->sdt, cdt, rho, Pp);
         if (act && !(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
-
-        // Lax-Wendroff increments and forward-Euler update
-        const long long row = (long long)y * pitch + xc;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
+            // increment d = sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x)),
+            // formed as w_down f(x+e) + w_up f(x-e) - c^2 f(x) (the terms
+            // cancel to d; every rounding is c^2 times smaller than f)
             S d = S(0);
             if (sx != 0) {
+                const S W = from_left(r0[i], h[i]);
+                const S E = from_right(r0[i], h[i]);
                 const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
-                const S e = E[i] - r0[i], w = W[i] - r0[i];
-                d = sx > 0 ? (wd * e + wu * w) : (wu * e + wd * w);
+                const S we = sx > 0 ? wd : wu, ww = sx > 0 ? wu : wd;
+                d = we * E + (ww * W - (wd + wu) * r0[i]);
             }
             if (sy != 0) {
                 const S wd = Weights<S>::get(P, 1, k, 0), wu = Weights<S>::get(P, 1, k, 1);
-                const S n = rp[i] - r0[i], s = rm[i] - r0[i];
-                d += sy > 0 ? (wd * n + wu * s) : (wu * n + wd * s);
+                const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
+                d += wn * rp[i] + (ws * rm[i] - (wd + wu) * r0[i]);
             }
-            const S out = r0[i] + (d - S(cdt[i]));
-            if (act) fo[(long long)i * plane + row] = out;
+            const S out = r0[i] + (d - cdt[i]);
+            if (act) (fo + (long long)i * plane)[o] = out;
         }
+    };
 
-        if (more) {
+    S A[16], B[16], Cw[16], D[16];
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                if (moves_y(i)) rm[i] = r0[i];
-                r0[i] = rp[i];
-            }
-            if (next_real) {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) rp[i] = rn[i];
-            } else {
-                ghost_row<S, C>(P, YHI, r0, rp);
-            }
-        }
+    for (int i = 0; i < 16; ++i) {
+        B[i] = ld(i, o_start);
+        Cw[i] = ld(i, o_start + pitch);
+        A[i] = moves_y(i) ? ld(i, o_start - pitch) : S(0);
+        D[i] = S(0);
+    }
+    // rows rotate through four register sets, so no copies between rows
+    unsigned o = o_start;
+    for (int y = y0; y < y1;) {
+        body(A, B, Cw, D, y, o); ++y; o += pitch;
+        if (y >= y1) break;
+        body(B, Cw, D, A, y, o); ++y; o += pitch;
+        if (y >= y1) break;
+        body(Cw, D, A, B, y, o); ++y; o += pitch;
+        if (y >= y1) break;
+        body(D, A, B, Cw, y, o); ++y; o += pitch;
     }
 }
 
@@ -323,71 +284,49 @@ __global__ __launch_bounds__(256) void step_kernel(const Inst* __restrict__ inst
 
 // ---------------------------------------------------------------- adjoint
 
-// Adjoint of one step on a periodic grid, per cell x (lam = lam^{n+1}):
+// Adjoint of one step on a periodic grid (the ghost ring of lam^{n+1} holds
+// the wrapped values), per cell x (lam = lam^{n+1}):
 //   lam^n(x) = lam(x) + LW^T(lam)(x) - dt (dC/df(x))^T lam(x)
-//   dt (dC/df)^T lam = M^T zeta,  zeta_k = s_k dt (Minv^T lam)_k (k >= 5),
-//                      zeta_{1..4} = -(d fhat^eq/d(rho,j,e))^T (s dt Minv^T lam)
-//   ds_k += -dt (fhat_k - fhat^eq_k) (Minv^T lam)_k
-// The equilibrium Jacobian comes from Dual4 evaluation of the same
-// equilibrium code the forward step runs.  Partial sums of ds per work item
-// go to `partial` (16 doubles per item), reduced by reduce_partials.
+// with the collision part from cell_adjoint (mrt_dual.h).  Partial sums of
+// the rate gradient per work item go to `partial` (16 doubles per item),
+// reduced in a fixed order by reduce_partials.
 template <typename S, typename C>
 __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int item, int x0, int y0,
                                              int y1, const S* __restrict__ lin,
                                              const S* __restrict__ fn, S* __restrict__ lout,
                                              double* __restrict__ partial) {
     const int lane = lane_id();
-    const int nx = P->nx, ny = P->ny, pitch = P->pitch;
+    const unsigned pitch = unsigned(P->pitch);
     const long long plane = P->plane;
     const S* __restrict__ li = lin + P->off;
     const S* __restrict__ fi = fn + P->off;
     S* __restrict__ lo = lout + P->off;
     const int x = x0 + lane;
-    const bool act = x < nx;
-    const int xc = act ? x : nx - 1;
+    const bool act = x < P->nx;
     const C b = C(P->b);
-    int hx = (lane == 0) ? x - 1 : x + 1;
-    hx = hx < 0 ? hx + nx : (hx >= nx ? hx - nx : hx);
-    const bool hload = (lane == 0 || lane == 63 || x == nx - 1);
-    const bool lone_last = x0 == nx - 1;
-    auto at = [&](int i, int yy, int xx) -> long long {
-        return (long long)i * plane + (long long)yy * pitch + xx;
-    };
+    const unsigned hoff = (lane == 0) ? unsigned(-1) : 1u;
+    const bool hload = (lane == 0 || lane == 63);
+    auto ldl = [&](int i, unsigned off) -> S { return (li + (long long)i * plane)[off]; };
+    auto ldf = [&](int i, unsigned off) -> S { return (fi + (long long)i * plane)[off]; };
     double acc[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-
-    for (int y = y0; y < y1; ++y) {
-        const int ym = y > 0 ? y - 1 : ny - 1;
-        const int yp = y + 1 < ny ? y + 1 : 0;
-        S l0[16], lm[16], lp[16], fc[16], h[16], W[16], E[16];
+    unsigned o = unsigned(P->origin) + unsigned(y0) * pitch + unsigned(x);
+    for (int y = y0; y < y1; ++y, o += pitch) {
+        S l0[16], lm[16], lp[16], fc[16], h[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            l0[i] = li[at(i, y, xc)];
-            fc[i] = fi[at(i, y, xc)];
-            if (moves_y(i)) {
-                lm[i] = li[at(i, ym, xc)];
-                lp[i] = li[at(i, yp, xc)];
-            }
+            l0[i] = ldl(i, o);
+            fc[i] = ldf(i, o);
+            lm[i] = moves_y(i) ? ldl(i, o - pitch) : S(0);
+            lp[i] = moves_y(i) ? ldl(i, o + pitch) : S(0);
+            h[i] = S(0);
         }
         if (hload) {
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                if (moves_x(i)) h[i] = li[at(i, y, hx)];
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) h[i] = S(0);
+                if (moves_x(i)) h[i] = ldl(i, o + hoff);
         }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            if (!moves_x(i)) continue;
-            W[i] = from_left(l0[i], h[i]);
-            E[i] = from_right(l0[i], h[i]);
-            if (x == nx - 1 && lane != 0 && lane != 63) E[i] = h[i];
-            if (lone_last && lane == 0) E[i] = nx == 1 ? l0[i] : li[at(i, y, 0)];
-        }
-
-        // collision part (moment space, Dual4 equilibrium Jacobian)
         C f[16], lam[16], coll[16], dsk[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -399,8 +338,6 @@ __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int ite
 #pragma unroll
             for (int k = 4; k < 16; ++k) acc[k] -= double(dsk[k]);
         }
-
-        const long long row = (long long)y * pitch + xc;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
@@ -408,8 +345,10 @@ __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int ite
             // transpose of the forward stencil: the weight that f(x+1) had in
             // F(x) now multiplies lam(x-1), and vice versa
             if (sx != 0) {
+                const S W = from_left(l0[i], h[i]);
+                const S E = from_right(l0[i], h[i]);
                 const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
-                const S e = E[i] - l0[i], w = W[i] - l0[i];
+                const S e = E - l0[i], w = W - l0[i];
                 d = sx > 0 ? (wd * w + wu * e) : (wu * w + wd * e);
             }
             if (sy != 0) {
@@ -418,7 +357,7 @@ __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int ite
                 d += sy > 0 ? (wd * s + wu * n) : (wu * s + wd * n);
             }
             const S out = l0[i] + (d - S(coll[i]));
-            if (act) lo[(long long)i * plane + row] = out;
+            if (act) (lo + (long long)i * plane)[o] = out;
         }
     }
     // wave reduction of the 12 non-trivial rate gradients
@@ -472,19 +411,22 @@ __global__ __launch_bounds__(256) void reduce_partials(const double* __restrict_
 
 // ------------------------------------------------------- per-cell kernels
 
+__device__ __forceinline__ long long cell_offset(const Inst* __restrict__ P, long long c) {
+    const int y = int(c / P->nx), x = int(c - (long long)y * P->nx);
+    return P->off + P->origin + (long long)y * P->pitch + x;
+}
+
 // f = Minv fhat^eq(rho, u, T) from row-major FP64 fields.
 template <typename S, typename C>
 __global__ __launch_bounds__(256) void init_kernel(const Inst* __restrict__ P, const double* rho,
                                                    const double* ux, const double* uy,
                                                    const double* T, S* __restrict__ f) {
-    const int nx = P->nx, ny = P->ny;
-    const long long n = (long long)nx * ny;
+    const long long n = (long long)P->nx * P->ny;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
-        const int y = int(c / nx), x = int(c - (long long)y * nx);
         C g[16];
         equilibrium_pops(C(rho[c]), C(ux[c]), C(uy[c]), C(T[c]), C(P->b), g);
-        S* base = f + P->off + (long long)y * P->pitch + x;
+        S* base = f + cell_offset(P, c);
 #pragma unroll
         for (int i = 0; i < 16; ++i) base[(long long)i * P->plane] = S(g[i]);
     }
@@ -496,12 +438,10 @@ __global__ __launch_bounds__(256) void moments_kernel(const Inst* __restrict__ P
                                                       const S* __restrict__ f, double* rho,
                                                       double* ux, double* uy, double* T,
                                                       unsigned* __restrict__ health) {
-    const int nx = P->nx, ny = P->ny;
-    const long long n = (long long)nx * ny;
+    const long long n = (long long)P->nx * P->ny;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
-        const int y = int(c / nx), x = int(c - (long long)y * nx);
-        const S* base = f + P->off + (long long)y * P->pitch + x;
+        const S* base = f + cell_offset(P, c);
         double g[16], m[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) g[i] = double(base[(long long)i * P->plane]);
@@ -520,12 +460,10 @@ __global__ __launch_bounds__(256) void moments_kernel(const Inst* __restrict__ P
 template <typename S>
 __global__ __launch_bounds__(256) void density_kernel(const Inst* __restrict__ P,
                                                       const S* __restrict__ f, double* rho) {
-    const int nx = P->nx, ny = P->ny;
-    const long long n = (long long)nx * ny;
+    const long long n = (long long)P->nx * P->ny;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
-        const int y = int(c / nx), x = int(c - (long long)y * nx);
-        const S* base = f + P->off + (long long)y * P->pitch + x;
+        const S* base = f + cell_offset(P, c);
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < 16; ++i) s += double(base[(long long)i * P->plane]);
@@ -536,12 +474,10 @@ template <typename S>
 __global__ __launch_bounds__(256) void density_adjoint_kernel(const Inst* __restrict__ P,
                                                               const double* g,
                                                               S* __restrict__ lam) {
-    const int nx = P->nx, ny = P->ny;
-    const long long n = (long long)nx * ny;
+    const long long n = (long long)P->nx * P->ny;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
-        const int y = int(c / nx), x = int(c - (long long)y * nx);
-        S* base = lam + P->off + (long long)y * P->pitch + x;
+        S* base = lam + cell_offset(P, c);
         const S v = S(g[c]);
 #pragma unroll
         for (int i = 0; i < 16; ++i) base[(long long)i * P->plane] = v;
@@ -553,16 +489,14 @@ template <typename S, typename C>
 __global__ __launch_bounds__(256) void init_adjoint_kernel(
     const Inst* __restrict__ P, const S* __restrict__ lam, const double* rho, const double* ux,
     const double* uy, const double* T, double* g_rho, double* g_ux, double* g_uy, double* g_T) {
-    const int nx = P->nx, ny = P->ny;
-    const long long n = (long long)nx * ny;
+    const long long n = (long long)P->nx * P->ny;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
-        const int y = int(c / nx), x = int(c - (long long)y * nx);
         Dual4<C> f[16];
         equilibrium_pops(Dual4<C>::var(C(rho[c]), 0), Dual4<C>::var(C(ux[c]), 1),
                          Dual4<C>::var(C(uy[c]), 2), Dual4<C>::var(C(T[c]), 3),
                          Dual4<C>(P->b), f);
-        const S* base = lam + P->off + (long long)y * P->pitch + x;
+        const S* base = lam + cell_offset(P, c);
         C g[4] = {C(0), C(0), C(0), C(0)};
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -581,27 +515,23 @@ __global__ __launch_bounds__(256) void init_adjoint_kernel(
 template <typename S>
 __global__ __launch_bounds__(256) void export_kernel(const Inst* __restrict__ P,
                                                      const S* __restrict__ f, double* out) {
-    const long long n = 16LL * P->nx * P->ny;
-    const int nx = P->nx, ny = P->ny;
+    const long long nc = (long long)P->nx * P->ny;
+    const long long n = 16 * nc;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
-        const long long i = c / ((long long)nx * ny);
-        const long long r = c - i * nx * ny;
-        const int y = int(r / nx), x = int(r - (long long)y * nx);
-        out[c] = double(f[P->off + i * P->plane + (long long)y * P->pitch + x]);
+        const long long i = c / nc;
+        out[c] = double(f[cell_offset(P, c - i * nc) + i * P->plane]);
     }
 }
 template <typename S>
 __global__ __launch_bounds__(256) void import_kernel(const Inst* __restrict__ P, const double* in,
                                                      S* __restrict__ f) {
-    const long long n = 16LL * P->nx * P->ny;
-    const int nx = P->nx, ny = P->ny;
+    const long long nc = (long long)P->nx * P->ny;
+    const long long n = 16 * nc;
     for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n;
          c += (long long)gridDim.x * blockDim.x) {
-        const long long i = c / ((long long)nx * ny);
-        const long long r = c - i * nx * ny;
-        const int y = int(r / nx), x = int(r - (long long)y * nx);
-        f[P->off + i * P->plane + (long long)y * P->pitch + x] = S(in[c]);
+        const long long i = c / nc;
+        f[cell_offset(P, c - i * nc) + i * P->plane] = S(in[c]);
     }
 }
 
@@ -626,6 +556,19 @@ namespace mrt {
 static int grid_for(long long n) {
     long long g = (n + 255) / 256;
     return int(g < 65536 ? (g > 0 ? g : 1) : 65536);
+}
+
+// Ghost ring of `count` instances (instance table `insts`, longest
+// perimeter 2 * (nx + ny) = perim) in buffer f.
+hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, bool force_periodic,
+                   hipStream_t st) {
+    const dim3 grid((perim + 255) / 256, count);
+    switch (prec) {
+        case 0: hipLaunchKernelGGL((ghost_kernel<double, double>), grid, dim3(256), 0, st, insts, static_cast<double*>(f), int(force_periodic)); break;
+        case 1: hipLaunchKernelGGL((ghost_kernel<float, float>), grid, dim3(256), 0, st, insts, static_cast<float*>(f), int(force_periodic)); break;
+        default: hipLaunchKernelGGL((ghost_kernel<float, double>), grid, dim3(256), 0, st, insts, static_cast<float*>(f), int(force_periodic)); break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,

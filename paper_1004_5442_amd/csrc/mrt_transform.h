@@ -237,14 +237,15 @@ MRT_HD void inverse_T(const C l[16], C z[16]) {
 //   12: (2P + rho(ux^2-uy^2)) ux     13: (-2P + rho(ux^2-uy^2)) uy
 //   14: 2(b+2) P^2/rho + (6+b) P u^2 + rho u^4
 //   15: ((b+4)P + rho u^2) ux uy     16: ((b+4)P + rho u^2)(ux^2 - uy^2)
-// Entries 0..3 are set to the conserved moments themselves.  Returns P.
+// Entries 0..3 are set to the conserved moments themselves.  binv = 1/b.
+// Returns P.
 template <typename C>
-MRT_HD C equilibrium_moments(C rho, C jx, C jy, C e, C b, C eq[16]) {
+MRT_HD C equilibrium_moments(C rho, C jx, C jy, C e, C b, C binv, C eq[16]) {
     const C ri = C(1) / rho;
     const C ux = jx * ri, uy = jy * ri;
     const C u2 = ux * ux + uy * uy;
     const C rhou2 = rho * u2;
-    const C P = (e - rhou2) / b;
+    const C P = (e - rhou2) * binv;
     const C d = ux * ux - uy * uy;
     const C rd = rho * d;
     const C q = (b + C(4)) * P + rhou2;
@@ -273,7 +274,7 @@ MRT_HD void equilibrium_pops(C rho, C ux, C uy, C T, C b, C f[16]) {
     const C jx = rho * ux, jy = rho * uy;
     const C e = b * rho * T + rho * (ux * ux + uy * uy);
     C m[16];
-    equilibrium_moments(rho, jx, jy, e, b, m);
+    equilibrium_moments(rho, jx, jy, e, b, C(1) / b, m);
     moments_to_pops(m, f);
 }
 
@@ -285,7 +286,7 @@ MRT_HD void collision_dt(const C f[16], C b, const C sdt[16], C out[16], C& rho,
     C m[16], eq[16], dm[16];
     pops_to_moments(f, m);
     rho = m[0];
-    P = equilibrium_moments(m[0], m[1], m[2], m[3], b, eq);
+    P = equilibrium_moments(m[0], m[1], m[2], m[3], b, C(1) / b, eq);
     dm[0] = dm[1] = dm[2] = dm[3] = C(0);
 #pragma unroll
     for (int k = 4; k < 16; ++k) dm[k] = sdt[k] * (m[k] - eq[k]);

@@ -51,7 +51,7 @@ _D = POINTER(c_double)
 _proto = {
     "mrt_init_grid": (c_int, [POINTER(c_void_p), c_int, c_int, c_int, POINTER(c_int), POINTER(c_void_p), c_void_p]),
     "mrt_population_bytes": (c_longlong, [c_int, c_int, c_int]),
-    "mrt_get_layout": (c_int, [c_void_p, POINTER(c_longlong), POINTER(c_longlong)]),
+    "mrt_get_layout": (c_int, [c_void_p, POINTER(c_longlong), POINTER(c_longlong), POINTER(c_longlong)]),
     "mrt_set_params": (c_int, [c_void_p, POINTER(Params)]),
     "mrt_set_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     "mrt_step": (c_int, [c_void_p, c_int]),

@@ -45,9 +45,9 @@ class Solver:
         L.check(L.raw().mrt_init_grid(byref(h), self.nx, self.ny, self.prec, bcs, ptrs,
                                       c_void_p(self.stream.cuda_stream)))
         self._h = h
-        pitch, plane = c_longlong(), c_longlong()
-        self._check(L.raw().mrt_get_layout(h, byref(pitch), byref(plane)))
-        self.pitch, self.plane = pitch.value, plane.value
+        pitch, plane, origin = c_longlong(), c_longlong(), c_longlong()
+        self._check(L.raw().mrt_get_layout(h, byref(pitch), byref(plane), byref(origin)))
+        self.pitch, self.plane, self.origin = pitch.value, plane.value, origin.value
         self.params = None
 
     # ------------------------------------------------------------ plumbing

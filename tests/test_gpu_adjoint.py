@@ -1,0 +1,139 @@
+"""GPU adjoint: per-step parity with the oracle's complex-step adjoint,
+full-gradient parity with the oracle reference gradient, and the 256^2 /
+500-step configuration against central finite differences."""
+import numpy as np
+import pytest
+
+from oracle import adjoint as oadj
+from oracle import mrt
+from paper_1004_5442_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+from paper_1004_5442_amd.adjoint import density_after  # noqa: E402
+from paper_1004_5442_amd.solver import Solver  # noqa: E402
+
+
+def _small_case(n=24, m=16, seed=0):
+    rng = np.random.default_rng(seed)
+    y, x = np.meshgrid((np.arange(m) + 0.5) / m, (np.arange(n) + 0.5) / n, indexing="ij")
+    rho = 1 + 0.05 * np.cos(2 * np.pi * (x + 2 * y)) + 0.02 * rng.standard_normal((m, n))
+    T = 1 + 0.05 * np.sin(2 * np.pi * (2 * x - y)) + 0.02 * rng.standard_normal((m, n))
+    s = W.rates(5e3, 1e4, 0.71, 1e4)
+    return rho, T, s, 1e-4, 1.0 / n, 1.0 / m
+
+
+def _padded(solver, arr16):
+    """(16, ny, nx) float64 -> device buffer in the solver's padded layout."""
+    buf = solver.empty_state()
+    dt = solver.storage_dtype
+    v = buf.view(dt)
+    idx = (np.arange(16)[:, None, None] * solver.plane + solver.origin
+           + np.arange(solver.ny)[None, :, None] * solver.pitch + np.arange(solver.nx)[None, None, :])
+    v[torch.as_tensor(idx.ravel(), device="cuda")] = torch.as_tensor(arr16.ravel(), device="cuda", dtype=dt)
+    return buf
+
+
+def _unpadded(solver, buf):
+    idx = (np.arange(16)[:, None, None] * solver.plane + solver.origin
+           + np.arange(solver.ny)[None, :, None] * solver.pitch + np.arange(solver.nx)[None, None, :])
+    return buf.view(solver.storage_dtype)[torch.as_tensor(idx.ravel(), device="cuda")].double().cpu().numpy().reshape(16, solver.ny, solver.nx)
+
+
+def test_adjoint_step_matches_oracle_fp64():
+    rho, T, s, dt, dx, dy = _small_case(70, 9)
+    ny, nx = rho.shape
+    p = mrt.Params(gamma=1.4, s=s, dt=dt, dx=dx, dy=dy)
+    rng = np.random.default_rng(1)
+    f = mrt.init_populations(rho, 0 * rho, 0 * rho, T, p) * (1 + 0.01 * rng.standard_normal((16, ny, nx)))
+    lam = rng.standard_normal((16, ny, nx))
+    want_lam, want_ds = oadj.adjoint_step(lam, f, p)
+    sv = Solver(nx, ny, "fp64")
+    sv.set_params(1.4, s, dt, dx, dy)
+    lam_d, f_d, out_d = _padded(sv, lam), _padded(sv, f), sv.empty_state()
+    ds = torch.zeros(16, dtype=torch.float64, device="cuda")
+    sv.adjoint_step(lam_d, f_d, out_d, ds)
+    got = _unpadded(sv, out_d)
+    assert np.max(np.abs(got - want_lam)) <= 1e-12 * np.abs(want_lam).max()
+    np.testing.assert_allclose(ds.cpu().numpy(), want_ds, rtol=1e-10, atol=1e-12 * np.abs(want_ds).max())
+
+
+def test_gradient_matches_oracle_reference_fp64():
+    rho, T, s, dt, dx, dy = _small_case()
+    ny, nx = rho.shape
+    N = 30
+    p = mrt.Params(gamma=1.4, s=s, dt=dt, dx=dx, dy=dy)
+    target = mrt.run(mrt.init_populations(rho, 0 * rho, 0 * rho, T + 0.01, p), p, N).sum(axis=0)
+    L_ref, g_ref = oadj.density_misfit_gradient(rho, 0 * rho, 0 * rho, T, target, p, N)
+    sv = Solver(nx, ny, "fp64")
+    r0 = torch.tensor(rho, device="cuda", requires_grad=True)
+    t0 = torch.tensor(T, device="cuda", requires_grad=True)
+    st = torch.tensor(s, device="cuda", requires_grad=True)
+    rhoN = density_after(r0, t0, st, sv, 1.4, dt, dx, dy, N, segment=7)
+    L = 0.5 * ((rhoN - torch.tensor(target, device="cuda")) ** 2).sum()
+    L.backward()
+    assert L.item() == pytest.approx(L_ref, rel=1e-10)
+    for name, g in (("rho", r0.grad), ("T", t0.grad), ("s", st.grad)):
+        want = g_ref[name]
+        got = g.detach().cpu().numpy()
+        assert np.max(np.abs(got - want)) <= 1e-9 * np.abs(want).max(), name
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-6), ("fp32_eq64", 1e-4)])
+def test_adjoint_configuration_against_finite_differences(precision, tol):
+    """256^2 periodic grid, 500 steps, loss = 1/2 |rho^N - rho_target|^2;
+    gradient w.r.t. rho0, T0 and s from the adjoint (sqrt(N) checkpoints)
+    against central differences of the FP64 forward on 32 seeded directions."""
+    case, T_target = W.adjoint_problem(n=256, seed=0, nsteps=500)
+    n, N = case.nx, case.nsteps
+    args = (1.4, case.dt, case.dx, case.dy, N)
+    s64 = Solver(n, n, "fp64")
+    rho0 = torch.tensor(case.rho, device="cuda")
+    T0 = torch.tensor(case.T, device="cuda")
+    s0 = torch.tensor(case.s, device="cuda")
+    with torch.no_grad():
+        target = density_after(rho0, torch.tensor(T_target, device="cuda"), s0, s64, *args)
+
+    def loss(r, t, s):
+        with torch.no_grad():
+            return float(0.5 * ((density_after(r, t, s, s64, *args) - target) ** 2).sum())
+
+    sv = s64 if precision == "fp64" else Solver(n, n, precision)
+    r = rho0.clone().requires_grad_(True)
+    t = T0.clone().requires_grad_(True)
+    sg = s0.clone().requires_grad_(True)
+    L = 0.5 * ((density_after(r, t, sg, sv, *args) - target) ** 2).sum()
+    L.backward()
+    rng = np.random.default_rng(2024)
+    worst = 0.0
+    for d in range(32):
+        dr = torch.tensor(rng.standard_normal((n, n)), device="cuda")
+        dT = torch.tensor(rng.standard_normal((n, n)), device="cuda")
+        # rates at s dt = 1 may move by at most ~3e-7 relative (within the
+        # library's 1e-6 slack on the [0, 1/dt] interval)
+        dsv = torch.tensor(rng.standard_normal(16), device="cuda") * s0 * 0.1
+        ad = float((r.grad * dr).sum() + (t.grad * dT).sum() + (sg.grad * dsv).sum())
+        eps = 1e-6
+        fd = (loss(rho0 + eps * dr, T0 + eps * dT, s0 + eps * dsv)
+              - loss(rho0 - eps * dr, T0 - eps * dT, s0 - eps * dsv)) / (2 * eps)
+        rel = abs(ad - fd) / abs(fd)
+        worst = max(worst, rel)
+    print(precision, "worst relative FD mismatch", worst)
+    assert worst < tol
+
+
+def test_checkpoint_segment_does_not_change_gradient():
+    rho, T, s, dt, dx, dy = _small_case(40, 24, seed=5)
+    sv = Solver(40, 24, "fp32_eq64")
+    grads = []
+    for seg in (1, 6, 50):
+        r0 = torch.tensor(rho, device="cuda", requires_grad=True)
+        rhoN = density_after(r0, torch.tensor(T, device="cuda"), torch.tensor(s, device="cuda"),
+                             sv, 1.4, dt, dx, dy, 37, segment=seg)
+        (rhoN ** 2).sum().backward()
+        grads.append(r0.grad.cpu().numpy())
+    assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[1], grads[2])

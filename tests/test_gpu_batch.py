@@ -1,0 +1,71 @@
+"""GPU parity of the batched form: many instances of different size,
+boundary kinds and parameters in one launch per step (captured graphs),
+each against its own oracle run."""
+import numpy as np
+import pytest
+
+from helpers import field_errors, fp32_tolerances, oracle_params, oracle_run, smooth_case
+from oracle import mrt
+from paper_1004_5442_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+from paper_1004_5442_amd.batch import Batch  # noqa: E402
+
+
+def _mixed_cases():
+    cases = [smooth_case(150, 37, ("eq", "outflow", "reflect", "reflect"), seed=1),
+             smooth_case(1, 7, ("periodic",) * 4, seed=2),
+             smooth_case(65, 1, ("outflow", "reflect", "eq", "outflow"), seed=3),
+             smooth_case(200, 4, ("reflect", "eq", "periodic", "periodic"), seed=4, gamma=5 / 3)]
+    cases += W.tube_batch(4, seed=9, nx_range=(200, 300))
+    return cases
+
+
+def test_fp64_batch_matches_oracle_across_graph_replays():
+    cases = _mixed_cases()
+    b = Batch(cases, "fp64")
+    b.set_tile(8)
+    states = [mrt.init_populations(c.rho, c.ux, c.uy, c.T, oracle_params(c)) for c in cases]
+    for replay in range(3):
+        print(f"replay {replay}", flush=True)
+        b.step(5)
+        for i, c in enumerate(cases):
+            p = oracle_params(c)
+            states[i] = mrt.run(states[i], p, 5)
+            got = b.populations(i)
+            assert np.max(np.abs(got - states[i])) <= 1e-12 * np.abs(states[i]).max(), (replay, c.name)
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp32"])
+def test_tube_batch_fp32_matches_oracle(precision):
+    cases = W.tube_batch(10, seed=3, nx_range=(200, 700))
+    b = Batch(cases, precision)
+    b.step(200)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 200)
+        err = field_errors(b.moments(i), mrt.macroscopic(want, p.b))
+        tol = fp32_tolerances(c, 200, want)
+        assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+
+
+def test_full_batch_512_tubes_sampled():
+    """The full batched workload (512 tubes, 1000 steps, FP32 + FP64
+    collision) in its autotuned launch; the three shortest tubes are
+    compared with the oracle."""
+    cases = W.tube_batch(512, seed=0)
+    b = Batch(cases, "fp32_eq64")
+    b.autotune(4)
+    b.step(1000)
+    order = np.argsort([c.nx for c in cases])[:3]
+    for i in order:
+        c = cases[i]
+        want, p = oracle_run(c, 1000)
+        err = field_errors(b.moments(int(i)), mrt.macroscopic(want, p.b))
+        tol = fp32_tolerances(c, 1000, want)
+        print(c.name, c.nx, err, tol, flush=True)
+        assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
