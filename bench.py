@@ -57,6 +57,89 @@ def time_solver(case, precision, steps, warmup, autotune=True):
     return {"mlups": mlups, "sec": sec, "ms_per_step": 1e3 * sec / steps, "tile": tile}
 
 
+def time_batch(steps, warmup):
+    """The batched form: 512 seeded shock tubes (nx 200..4000, ny 4), FP32
+    populations with FP64 collision, graph-captured steps."""
+    import torch
+
+    from paper_1004_5442_amd import workloads as W
+    from paper_1004_5442_amd.batch import Batch
+    cases = W.tube_batch(512, seed=0)
+    b = Batch(cases, "fp32_eq64")
+    b.autotune(4)
+    b.step(warmup)
+    torch.cuda.synchronize()
+    sec = _events_time(torch.cuda.current_stream(), b.step, steps)
+    b.moments(0)              # raises if any instance went unhealthy
+    cells = b.cells
+    tile = b.tile()
+    b.close()
+    return {"mlups": round(cells * steps / sec / 1e6, 1), "cells": cells, "instances": len(cases),
+            "ms_per_step": round(1e3 * sec / steps, 4), "tile_rows": tile[0],
+            "roofline_frac": round(cells * 128 * steps / sec / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def time_adjoint(steps):
+    """Adjoint step vs forward step on the 256^2 periodic adjoint workload
+    (FP32 storage, FP64 collision), and one full gradient (500-step forward,
+    sqrt(N) checkpoints, backward) vs the plain 500-step forward."""
+    import torch
+
+    from paper_1004_5442_amd import workloads as W
+    from paper_1004_5442_amd.adjoint import density_after
+    from paper_1004_5442_amd.solver import Solver
+    case, T_target = W.adjoint_problem(n=256, seed=0, nsteps=500)
+    n = case.nx
+    sv = Solver(n, n, "fp32_eq64")
+    sv.set_params(case.gamma, case.s, case.dt, case.dx, case.dy)
+    rho0 = torch.tensor(case.rho, device="cuda")
+    T0 = torch.tensor(case.T, device="cuda")
+    zero = torch.zeros_like(rho0)
+    f, g = sv.empty_state(), sv.empty_state()
+    sv.init_buffer(rho0, zero, zero, T0, f)
+    lam, lam2 = sv.empty_state(), sv.empty_state()
+    sv.init_buffer(rho0, zero, zero, T0, lam)
+    ds = torch.zeros(16, dtype=torch.float64, device="cuda")
+
+    def fwd(k):
+        for _ in range(k):
+            sv.step_buffers(f, g)
+
+    def adj(k):
+        for _ in range(k):
+            sv.adjoint_step(lam, f, lam2, ds)
+
+    fwd(5)
+    adj(5)
+    st = torch.cuda.current_stream()
+    t_f = _events_time(st, fwd, steps) / steps
+    t_a = _events_time(st, adj, steps) / steps
+    args = (case.gamma, case.dt, case.dx, case.dy, case.nsteps)
+    s0 = torch.tensor(case.s, device="cuda")
+    with torch.no_grad():
+        target = density_after(rho0, torch.tensor(T_target, device="cuda"), s0, sv, *args)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        density_after(rho0, T0, s0, sv, *args)
+    torch.cuda.synchronize()
+    t_fwd_full = time.perf_counter() - t0
+    r = rho0.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    L = 0.5 * ((density_after(r, T0, s0, sv, *args) - target) ** 2).sum()
+    L.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t0
+    sv.close()
+    return {"grid": f"{n}x{n}", "adjoint_step_ms": round(1e3 * t_a, 4), "forward_step_ms": round(1e3 * t_f, 4),
+            "adjoint_over_forward": round(t_a / t_f, 3),
+            "adjoint_mlups": round(n * n / t_a / 1e6, 1),
+            "adjoint_roofline_frac": round(n * n * 192 / t_a / 1e9 / HBM_PEAK_GBS, 4),
+            "gradient_500_steps_s": round(t_grad, 4), "forward_500_steps_s": round(t_fwd_full, 4),
+            "gradient_over_forward": round(t_grad / t_fwd_full, 3),
+            "note": "256^2 FP32 fits the Infinity Cache: effective, not HBM, bandwidth"}
+
+
 def roofline(case, precision, r):
     per_launch_bytes = BYTES_PER_SITE[precision] * case.cells
     achieved = per_launch_bytes / (r["sec"] / r["steps"]) / 1e9
@@ -158,6 +241,8 @@ def main():
                 "mlups": round(rr["mlups"], 1),
                 "effective_GBs": roofline(rp, pr, rr)["achieved"],
                 "note": "fits the 256 MB Infinity Cache: effective, not HBM, bandwidth"}
+        extra["batched_512_tubes"] = time_batch(max(50, args.steps // 2), 5)
+        extra["adjoint_256"] = time_adjoint(100)
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

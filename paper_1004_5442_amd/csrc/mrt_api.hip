@@ -19,7 +19,7 @@
 #include "../../include/mrtlb.h"
 
 namespace mrt {
-hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, bool force_periodic,
+hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, int mode,
                    hipStream_t st);
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                   void* fout, unsigned* health, int grid, hipStream_t st);
@@ -50,12 +50,13 @@ namespace {
 size_t elem_size(int prec) { return prec == MRT_FP64 ? 8 : 4; }
 
 // Population layout per plane: rows -1..ny of `pitch` elements (pitch a
-// multiple of 64 >= nx + 2, so every row starts 256-byte aligned and the
-// ghost columns x = -1 / x = nx fit in the row padding), preceded by one
+// multiple of 256 >= nx + 3, so every row starts 256-byte aligned, the ghost
+// columns x = -1 / x = nx and the never-read column nx + 1 fit in the row
+// padding, and a 256-column work item never leaves its row), preceded by one
 // 64-element block; cell (0, 0) sits at `origin`.  The plane stride adds an
-// odd number of 64-element blocks so the 16 planes of one row are not a large
-// power of two apart.
-long long pitch_for(int nx) { return ((long long)nx + 2 + 63) / 64 * 64; }
+// odd number of 64-element blocks so the 16 planes of one row are not a
+// large power of two apart.
+long long pitch_for(int nx) { return ((long long)nx + 3 + 255) / 256 * 256; }
 long long origin_for(int nx) { return pitch_for(nx) + 64; }
 long long plane_for(int nx, int ny) { return (long long)(ny + 2) * pitch_for(nx) + 128 + 5 * 64; }
 
@@ -118,21 +119,33 @@ int fill_inst(Inst& I, int nx, int ny, const int bc[4], const mrt_params* p, std
             mrt::equilibrium_pops<double>(st[0], st[1], st[2], st[3], I.b, I.ghost[side]);
         }
     }
-    (void)nx;
-    (void)ny;
+    // where out-of-grid neighbours are read (see Inst)
+    auto lo = [](int kind, int n) { return kind == MRT_BC_PERIODIC ? n - 1 : (kind == MRT_BC_OUTFLOW ? 0 : -1); };
+    auto hi = [](int kind, int n) { return kind == MRT_BC_PERIODIC ? 0 : (kind == MRT_BC_OUTFLOW ? n - 1 : n); };
+    I.col_lo = lo(bc[0], nx);
+    I.col_hi = hi(bc[1], nx);
+    I.row_lo = lo(bc[2], ny);
+    I.row_hi = hi(bc[3], ny);
     return MRT_OK;
 }
 
-// Work items of one instance: 64-column strips x bands of `rows` rows.
+bool has_kind(const int bc[4], int kind) {
+    for (int k = 0; k < 4; ++k)
+        if (bc[k] == kind) return true;
+    return false;
+}
+
+// Work items of one instance: 256-column chunks x bands of `rows` rows.
 void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
     for (int y0 = 0; y0 < ny; y0 += rows)
-        for (int x0 = 0; x0 < nx; x0 += 64)
+        for (int x0 = 0; x0 < nx; x0 += 256)
             items.push_back(Item{inst, x0, y0, std::min(ny, y0 + rows)});
 }
 
+// enough items for ~2048 blocks (8192 waves) when the grid allows it
 int default_rows(int nx, int ny) {
-    const long long strips = (nx + 63) / 64;
-    long long r = (strips * ny + 8191) / 8192;
+    const long long chunks = (nx + 255) / 256;
+    long long r = (chunks * ny + 2047) / 2048;
     r = std::max<long long>(4, std::min<long long>(r, 256));
     return int(std::min<long long>(r, ny));
 }
@@ -161,7 +174,7 @@ struct mrt_ctx {
     Item* d_items = nullptr;
     int nitems = 0, rows = 0, grid = 0;
     double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
-    double* d_partial = nullptr;     // 16 doubles per work item: adjoint partial sums
+    double* d_partial = nullptr;     // 16 doubles per wave of a work item: adjoint partial sums
     unsigned* d_health = nullptr;
     bool params_set = false, fields_set = false;
     std::string err;
@@ -174,6 +187,16 @@ int ctx_fail(mrt_ctx* c, int code, const std::string& msg) {
     return code;
 }
 
+// Equilibrium ghosts of MRT_BC_EQ sides into both population buffers (they
+// are never overwritten by a step).
+int fill_eq_ghosts(mrt_ctx* c) {
+    std::string& ctx_err = c->err;
+    if (!has_kind(c->bc, MRT_BC_EQ)) return MRT_OK;
+    for (int k = 0; k < 2; ++k)
+        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), c->f[k], 2, c->stream));
+    return MRT_OK;
+}
+
 int build_items(mrt_ctx* c, int rows) {
     std::string& ctx_err = c->err;
     std::vector<Item> items;
@@ -184,7 +207,7 @@ int build_items(mrt_ctx* c, int rows) {
     c->d_partial = nullptr;
     HIPTRY(hipMalloc(&c->d_items, items.size() * sizeof(Item)));
     HIPTRY(hipMemcpy(c->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
-    HIPTRY(hipMalloc(&c->d_partial, items.size() * 16 * sizeof(double)));
+    HIPTRY(hipMalloc(&c->d_partial, items.size() * 4 * 16 * sizeof(double)));
     c->nitems = int(items.size());
     c->rows = rows;
     return MRT_OK;
@@ -281,8 +304,12 @@ int mrt_set_params(mrt_ctx* c, const mrt_params* p) {
     if (rc != MRT_OK) return rc;
     c->inst = I;
     HIPTRY(hipMemcpyAsync(c->d_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
-    HIPTRY(hipStreamSynchronize(c->stream));
     c->params_set = true;
+    if (c->fields_set) {
+        const int r = fill_eq_ghosts(c);
+        if (r != MRT_OK) return r;
+    }
+    HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
 }
 
@@ -305,9 +332,11 @@ int mrt_set_fields(mrt_ctx* c, const double* rho, const double* ux, const double
         HIPTRY(hipMemcpyAsync(s + 2 * n, uy, b, hipMemcpyHostToDevice, c->stream));
         HIPTRY(hipMemcpyAsync(s + 3 * n, T, b, hipMemcpyHostToDevice, c->stream));
         HIPTRY(mrt::k_init(c->prec, c->d_inst, n, s, s + n, s + 2 * n, s + 3 * n, c->f[c->cur], c->stream));
-        HIPTRY(hipStreamSynchronize(c->stream));
     }
     c->fields_set = true;
+    const int r = fill_eq_ghosts(c);
+    if (r != MRT_OK) return r;
+    if (!on_device) HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
 }
 
@@ -317,8 +346,9 @@ int mrt_step(mrt_ctx* c, int n) {
     if (n < 0) return ctx_fail(c, MRT_EINVAL, "n < 0");
     if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
     const int perim = 2 * (c->nx + c->ny);
+    const bool reflect = has_kind(c->bc, MRT_BC_REFLECT);
     for (int k = 0; k < n; ++k) {
-        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[c->cur], false, c->stream));
+        if (reflect) HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[c->cur], 1, c->stream));
         HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[c->cur], c->f[1 - c->cur],
                            c->d_health, c->grid, c->stream));
         c->cur ^= 1;
@@ -331,8 +361,9 @@ int mrt_step_buffers(mrt_ctx* c, const void* fin, void* fout) {
     std::string& ctx_err = c->err;
     if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
     if (!fin || !fout || fin == fout) return ctx_fail(c, MRT_EINVAL, "need two distinct buffers");
-    HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(fin), false,
-                        c->stream));
+    if (has_kind(c->bc, MRT_BC_EQ) || has_kind(c->bc, MRT_BC_REFLECT))
+        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(fin), 3,
+                            c->stream));
     HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, fin, fout, c->d_health, c->grid,
                        c->stream));
     return MRT_OK;
@@ -388,9 +419,11 @@ int mrt_set_populations(mrt_ctx* c, const double* f, int on_device) {
         HIPTRY(hipMemcpyAsync(tmp, f, sizeof(double) * 16 * size_t(n), hipMemcpyHostToDevice, c->stream));
         HIPTRY(mrt::k_import(c->prec, c->d_inst, n, tmp, c->f[c->cur], c->stream));
         HIPTRY(hipFreeAsync(tmp, c->stream));
-        HIPTRY(hipStreamSynchronize(c->stream));
     }
     c->fields_set = true;
+    const int r = fill_eq_ghosts(c);
+    if (r != MRT_OK) return r;
+    if (!on_device) HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
 }
 
@@ -507,8 +540,6 @@ int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* la
     if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
     if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
         return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
-    HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(lam_next),
-                        true, c->stream));
     HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items, c->nitems, lam_next, f_n, lam_n,
                           c->d_partial, ds, c->stream));
     return MRT_OK;
@@ -547,6 +578,8 @@ int mrt_init_buffer(mrt_ctx* c, const double* rho, const double* ux, const doubl
     std::string& ctx_err = c->err;
     if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
     HIPTRY(mrt::k_init(c->prec, c->d_inst, (long long)c->nx * c->ny, rho, ux, uy, T, f, c->stream));
+    if (has_kind(c->bc, MRT_BC_EQ))
+        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), f, 2, c->stream));
     return MRT_OK;
 }
 
@@ -561,6 +594,7 @@ struct mrt_batch {
     std::vector<long long> cells;
     long long total_cells = 0, total_elems = 0, max_cells = 0;
     int max_perim = 0;
+    bool any_reflect = false;
     void* f[2] = {nullptr, nullptr};
     int cur = 0;
     Inst* d_insts = nullptr;
@@ -624,6 +658,7 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
         I.origin = int(origin_for(d.nx));
         I.plane = plane_for(d.nx, d.ny);
         b->max_perim = std::max(b->max_perim, 2 * (d.nx + d.ny));
+        b->any_reflect = b->any_reflect || has_kind(d.bc, MRT_BC_REFLECT);
         I.off = off;
         std::string e;
         if (fill_inst(I, d.nx, d.ny, d.bc, &d.params, e) != MRT_OK) {
@@ -675,6 +710,10 @@ int mrt_batch_set_fields(mrt_batch* b, int i, const double* rho, const double* u
     HIPTRY(hipMemcpyAsync(s + 2 * n, uy, by, hipMemcpyHostToDevice, b->stream));
     HIPTRY(hipMemcpyAsync(s + 3 * n, T, by, hipMemcpyHostToDevice, b->stream));
     HIPTRY(mrt::k_init(b->prec, b->d_insts + i, n, s, s + n, s + 2 * n, s + 3 * n, b->f[b->cur], b->stream));
+    // equilibrium ghosts of this instance in both buffers
+    const int perim = 2 * (b->insts[i].nx + b->insts[i].ny);
+    for (int k = 0; k < 2; ++k)
+        HIPTRY(mrt::k_ghost(b->prec, b->d_insts + i, 1, perim, b->f[k], 2, b->stream));
     HIPTRY(hipStreamSynchronize(b->stream));
     return MRT_OK;
 }
@@ -693,7 +732,8 @@ int mrt_batch_step(mrt_batch* b, int n) {
         HIPTRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         int c = b->cur;
         for (int k = 0; k < n; ++k) {
-            hipError_t e = mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[c], false, cap);
+            hipError_t e = hipSuccess;
+            if (b->any_reflect) e = mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[c], 1, cap);
             if (e == hipSuccess)
                 e = mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[c], b->f[1 - c],
                                 b->d_health, b->grid, cap);

@@ -15,11 +15,16 @@ enum { BC_PERIODIC = 0, BC_EQ = 1, BC_OUTFLOW = 2, BC_REFLECT = 3 };
 struct Inst {
     long long off;      // element offset of population plane 0 in the buffers
     long long plane;    // elements between population planes
-    int nx, ny, pitch;  // pitch >= nx + 2 and a multiple of 64
+    int nx, ny, pitch;  // pitch >= nx + 3 and a multiple of 256
     int origin;         // offset of cell (0, 0) in a plane; cell (x, y) of plane i
                         // is at off + i * plane + origin + y * pitch + x for
                         // -1 <= x <= nx, -1 <= y <= ny (x or y outside [0, n):
-                        // the ghost ring)
+                        // the ghost ring; column nx + 1 is never read)
+    // Where a neighbour outside the grid is read from: column col_lo for
+    // x = -1 and col_hi for x >= nx, row row_lo for y = -1 and row_hi for
+    // y = ny.  Periodic sides point at the wrapped cell, outflow sides at the
+    // adjacent cell, fixed-equilibrium and reflecting sides at the ghost ring.
+    int col_lo, col_hi, row_lo, row_hi;
     int item0;          // first work item of this instance (partial-sum rows)
     int pad0;
     int bc[4];
@@ -37,8 +42,9 @@ struct Inst {
     double ghost[4][16];   // f^eq of each MRT_BC_EQ side
 };
 
-// Work item: one wave advances 64 columns [x0, x0 + 64) of rows [y0, y1) of
-// instance `inst`.
+// Work item of the step kernel: one block of 4 waves advances 256 columns
+// [x0, x0 + 256) of rows [y0, y1) of instance `inst`; the adjoint kernel
+// splits the same item into four 64-column waves.
 struct Item {
     int inst, x0, y0, y1;
 };

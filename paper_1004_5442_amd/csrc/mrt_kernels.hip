@@ -122,102 +122,154 @@ struct Weights<double> {
 
 // ------------------------------------------------------------------ ghosts
 
-// Fill the ghost ring of one instance (x = -1 and x = nx for 0 <= y < ny;
-// y = -1 and y = ny for 0 <= x < nx) from the current populations:
-// periodic -> the wrapped cell, MRT_BC_EQ -> the side's equilibrium,
-// outflow -> the adjacent cell, reflecting -> the equilibrium of the
-// adjacent cell with its normal velocity reversed.  Corners are never read.
+// Ghost cells that are not read through the index remap of Inst: the
+// equilibria of MRT_BC_EQ sides (written once per buffer, `mode` bit 1) and
+// the reflected equilibria of MRT_BC_REFLECT sides (rewritten before every
+// step from the adjacent cell with its normal velocity reversed, `mode`
+// bit 0).  Ghosts x = -1 / x = nx for 0 <= y < ny, y = -1 / y = ny for
+// 0 <= x < nx; corners are never read.
 template <typename S, typename C>
 __global__ __launch_bounds__(256) void ghost_kernel(const Inst* __restrict__ insts,
-                                                    S* __restrict__ f, int force_periodic) {
+                                                    S* __restrict__ f, int mode) {
     const Inst* __restrict__ P = insts + blockIdx.y;
     const int nx = P->nx, ny = P->ny;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * (nx + ny)) return;
-    int side, gx, gy, ix, iy, px, py;
+    int side, gx, gy, ix, iy;
     if (t < ny) {
-        side = XLO; gx = -1; gy = t; ix = 0; iy = t; px = nx - 1; py = t;
+        side = XLO; gx = -1; gy = t; ix = 0; iy = t;
     } else if (t < 2 * ny) {
-        side = XHI; gx = nx; gy = t - ny; ix = nx - 1; iy = gy; px = 0; py = gy;
+        side = XHI; gx = nx; gy = t - ny; ix = nx - 1; iy = gy;
     } else if (t < 2 * ny + nx) {
-        side = YLO; gx = t - 2 * ny; gy = -1; ix = gx; iy = 0; px = gx; py = ny - 1;
+        side = YLO; gx = t - 2 * ny; gy = -1; ix = gx; iy = 0;
     } else {
-        side = YHI; gx = t - 2 * ny - nx; gy = ny; ix = gx; iy = ny - 1; px = gx; py = 0;
+        side = YHI; gx = t - 2 * ny - nx; gy = ny; ix = gx; iy = ny - 1;
     }
-    const int kind = force_periodic ? int(BC_PERIODIC) : P->bc[side];
+    const int kind = P->bc[side];
+    const bool do_eq = kind == BC_EQ && (mode & 2);
+    const bool do_ref = kind == BC_REFLECT && (mode & 1);
+    if (!do_eq && !do_ref) return;
     S* __restrict__ base = f + P->off + P->origin;
     const long long plane = P->plane;
     const long long go = (long long)gy * P->pitch + gx;
     S g[16];
-    if (kind == BC_EQ) {
+    if (do_eq) {
 #pragma unroll
         for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[side][i]);
     } else {
-        const bool per = kind == BC_PERIODIC;
-        const long long so = (long long)(per ? py : iy) * P->pitch + (per ? px : ix);
-        S c[16];
+        const long long so = (long long)iy * P->pitch + ix;
+        C fc[16], m[16], eq[16], out[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) c[i] = base[i * plane + so];
-        if (kind == BC_REFLECT) {
-            C fc[16], m[16], eq[16], out[16];
+        for (int i = 0; i < 16; ++i) fc[i] = C(base[i * plane + so]);
+        pops_to_moments(fc, m);
+        const bool nxs = side == XLO || side == XHI;
+        equilibrium_moments(m[0], nxs ? -m[1] : m[1], nxs ? m[2] : -m[2], m[3], C(P->b),
+                            C(P->binv), eq);
+        moments_to_pops(eq, out);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) fc[i] = C(c[i]);
-            pops_to_moments(fc, m);
-            const bool nxs = side == XLO || side == XHI;
-            equilibrium_moments(m[0], nxs ? -m[1] : m[1], nxs ? m[2] : -m[2], m[3], C(P->b),
-                                C(P->binv), eq);
-            moments_to_pops(eq, out);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) g[i] = S(out[i]);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) g[i] = c[i];
-        }
+        for (int i = 0; i < 16; ++i) g[i] = S(out[i]);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) base[i * plane + go] = g[i];
 }
 
+// offset in a plane of row y, -1 <= y <= ny, with the boundary remap
+__device__ __forceinline__ unsigned row_offset(const Inst* __restrict__ P, int y) {
+    const int r = y < 0 ? P->row_lo : (y >= P->ny ? P->row_hi : y);
+    return unsigned(P->origin + r * P->pitch);
+}
+
 // ------------------------------------------------------------------- step
 
-// Advance one work item: columns [x0, x0+64) of rows [y0, y1) of one
-// instance.  The ghost ring holds every out-of-grid neighbour, so all
-// neighbours are plain loads: rows y-1 / y+1 from the register window,
-// columns x-1 / x+1 from the adjacent lanes (DPP wavefront shifts) and, on
-// lanes 0 and 63, from one halo load.  Lanes past the last column load the
-// ghost column / padding (in bounds: the pitch covers x0 + 64) and store
-// nothing.
+// One work item is a block of 4 waves covering 256 columns [x0, x0 + 256)
+// of rows [y0, y1) of one instance (the row pitch is a multiple of 256, so
+// the block never leaves its rows).  Lane l of wave w owns column
+// x0 + 64 w + l and the block marches up the band together:
+//  * rows y-1 / y+1 come from a register window (four register sets rotate,
+//    no copies), row y+2 is prefetched while row y is computed;
+//  * columns x-1 / x+1 come from the adjacent lanes by DPP wavefront shifts;
+//    the edge lanes of the four waves swap their values through LDS (double
+//    buffered, one barrier per row) and only lanes 0 of wave 0 and 63 of
+//    wave 3 load a halo column from memory;
+//  * out-of-grid neighbours come through the boundary remap of Inst (the
+//    wrapped or adjacent cell, or the ghost ring), so there is no boundary
+//    code; lanes past the last column compute on those values and store
+//    into column nx + 1, which is never read.
+constexpr int kWaves = 4;
+
+template <typename S>
+struct EdgeBuf {
+    // [slot][wave][0: lane 0, 1: lane 63][x-moving population]
+    S v[2][kWaves][2][12];
+};
+
+// index of an x-moving population among the 12 (0, 2, 4, 6, 8..15)
+constexpr int xslot(int i) { return i < 8 ? i >> 1 : i - 4; }
+
 template <typename S, typename C, bool COMP>
-__device__ __forceinline__ void step_item(const Inst* __restrict__ P, int x0, int y0, int y1,
-                                          const S* __restrict__ fin, S* __restrict__ fout,
-                                          unsigned* __restrict__ health) {
+__device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, int y0, int y1,
+                                           const S* __restrict__ fin, S* __restrict__ fout,
+                                           unsigned* __restrict__ health, EdgeBuf<S>& lds) {
     const int lane = lane_id();
-    const unsigned pitch = unsigned(P->pitch);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long plane = P->plane;
     const S* __restrict__ fi = fin + P->off;
     S* __restrict__ fo = fout + P->off;
-    const int x = x0 + lane;
-    const bool act = x < P->nx;
+    const int nx = P->nx;
+    const int x = x0 + 64 * wv + lane;
+    const bool act = x < nx;
+    // per-lane load column (lanes past the grid read the x >= nx neighbour)
+    // and store column (lanes past the grid write the unread column nx + 1)
+    const unsigned cx = unsigned(act ? x : P->col_hi);
+    const unsigned xs = unsigned(act ? x : nx + 1);
     const C b = C(P->b), binv = C(P->binv);
-    // uniform plane base + 32-bit lane offset (global_load with saddr)
-    auto ld = [&](int i, unsigned off) -> S { return (fi + (long long)i * plane)[off]; };
-    const unsigned hoff = (lane == 0) ? unsigned(-1) : 1u;   // halo column relative to x
-    const bool hload = (lane == 0 || lane == 63);
-    const unsigned o_start = unsigned(P->origin) + unsigned(y0) * pitch + unsigned(x);
+    // uniform row offset + per-lane column, summed in 32 bits (the ghost
+    // column is col = -1: row + col is then row - 1 >= 63; row >= 64)
+    auto ld = [&](int i, unsigned row, unsigned col) -> S {
+        return (fi + (long long)i * plane)[row + col];
+    };
+    // the two lanes that load a halo column from memory
+    const bool hmem = (wv == 0 && lane == 0) || (wv == kWaves - 1 && lane == 63);
+    unsigned hx = cx;
+    if (wv == 0 && lane == 0) hx = unsigned(x0 > 0 ? x0 - 1 : P->col_lo);
+    if (wv == kWaves - 1 && lane == 63) hx = unsigned(x0 + 256 < nx ? x0 + 256 : P->col_hi);
+    const bool edge_lane = lane == 0 || lane == 63;
+    const int eside = lane == 0 ? 0 : 1;
+    // neighbour wave whose edge value this lane needs (lane 0: west wave's
+    // lane 63; lane 63: east wave's lane 0)
+    const int nwave = lane == 0 ? wv - 1 : wv + 1;
+    const int nside = lane == 0 ? 1 : 0;
+    const bool hlds = edge_lane && !hmem;
+
+    auto publish = [&](const S (&r)[16], int slot) {
+        if (edge_lane) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (moves_x(i)) lds.v[slot][wv][eside][xslot(i)] = r[i];
+        }
+    };
 
     auto body = [&](const S (&rm)[16], const S (&r0)[16], const S (&rp)[16], S (&rn)[16],
-                    int y, unsigned o) {
-        if (y + 1 < y1) {
+                    int y) {
+        const bool more = y + 1 < y1;
+        if (more) {
+            const unsigned on = row_offset(P, y + 2);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) rn[i] = ld(i, o + 2 * pitch);
+            for (int i = 0; i < 16; ++i) rn[i] = ld(i, on, cx);
         }
+        const unsigned o = row_offset(P, y);
         S h[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) h[i] = S(0);
-        if (hload) {
+        if (hmem) {
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                if (moves_x(i)) h[i] = ld(i, o + hoff);
+                if (moves_x(i)) h[i] = ld(i, o, hx);
+        } else if (hlds) {
+            const int slot = y & 1;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (moves_x(i)) h[i] = lds.v[slot][nwave][nside][xslot(i)];
         }
         S cdt[16];
         C rho, Pp;
@@ -228,7 +280,7 @@ __device__ __forceinline__ void step_item(const Inst* __restrict__ P, int x0, in
             const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
             // increment d = sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x)),
             // formed as w_down f(x+e) + w_up f(x-e) - c^2 f(x) (the terms
-            // cancel to d; every rounding is c^2 times smaller than f)
+            // cancel to d; every rounding is c times smaller than f)
             S d = S(0);
             if (sx != 0) {
                 const S W = from_left(r0[i], h[i]);
@@ -242,29 +294,35 @@ __device__ __forceinline__ void step_item(const Inst* __restrict__ P, int x0, in
                 const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
                 d += wn * rp[i] + (ws * rm[i] - (wd + wu) * r0[i]);
             }
-            const S out = r0[i] + (d - cdt[i]);
-            if (act) (fo + (long long)i * plane)[o] = out;
+            (fo + (long long)i * plane)[o + xs] = r0[i] + (d - cdt[i]);
         }
+        // hand row y+1's edge values to the neighbour waves
+        if (more) publish(rp, (y + 1) & 1);
+        __syncthreads();
     };
 
     S A[16], B[16], Cw[16], D[16];
+    {
+        const unsigned om = row_offset(P, y0 - 1), o0 = row_offset(P, y0), op = row_offset(P, y0 + 1);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        B[i] = ld(i, o_start);
-        Cw[i] = ld(i, o_start + pitch);
-        A[i] = moves_y(i) ? ld(i, o_start - pitch) : S(0);
-        D[i] = S(0);
+        for (int i = 0; i < 16; ++i) {
+            B[i] = ld(i, o0, cx);
+            Cw[i] = ld(i, op, cx);
+            A[i] = moves_y(i) ? ld(i, om, cx) : S(0);
+            D[i] = S(0);
+        }
     }
+    publish(B, y0 & 1);
+    __syncthreads();
     // rows rotate through four register sets, so no copies between rows
-    unsigned o = o_start;
     for (int y = y0; y < y1;) {
-        body(A, B, Cw, D, y, o); ++y; o += pitch;
+        body(A, B, Cw, D, y); ++y;
         if (y >= y1) break;
-        body(B, Cw, D, A, y, o); ++y; o += pitch;
+        body(B, Cw, D, A, y); ++y;
         if (y >= y1) break;
-        body(Cw, D, A, B, y, o); ++y; o += pitch;
+        body(Cw, D, A, B, y); ++y;
         if (y >= y1) break;
-        body(D, A, B, Cw, y, o); ++y; o += pitch;
+        body(D, A, B, Cw, y); ++y;
     }
 }
 
@@ -273,19 +331,26 @@ __global__ __launch_bounds__(256) void step_kernel(const Inst* __restrict__ inst
                                                    const Item* __restrict__ items, int nitems,
                                                    const S* __restrict__ fin, S* __restrict__ fout,
                                                    unsigned* __restrict__ health) {
-    const int wpb = blockDim.x >> 6;
-    int w = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const int nw = gridDim.x * wpb;
-    for (; w < nitems; w += nw) {
+    __shared__ EdgeBuf<S> lds;
+    // Workgroups are dealt round-robin to the 8 XCDs (workgroup g -> XCD
+    // g % 8), each with its own L2.  Ordinal q of the launch runs item
+    // (q % 8) * per + q / 8, so every XCD sweeps one contiguous run of the
+    // item table (row bands, x fastest) and neighbouring items, which share
+    // halo cache lines, meet in the same L2 at about the same time.
+    const int per = (nitems + 7) >> 3;
+    for (int q = blockIdx.x; q < 8 * per; q += gridDim.x) {
+        const int w = (q & 7) * per + (q >> 3);
+        if (w >= nitems) continue;
         const Item it = items[w];
-        step_item<S, C, COMP>(insts + it.inst, it.x0, it.y0, it.y1, fin, fout, health);
+        step_block<S, C, COMP>(insts + it.inst, it.x0, it.y0, it.y1, fin, fout, health, lds);
+        __syncthreads();   // the next item reuses the edge buffer
     }
 }
 
 // ---------------------------------------------------------------- adjoint
 
-// Adjoint of one step on a periodic grid (the ghost ring of lam^{n+1} holds
-// the wrapped values), per cell x (lam = lam^{n+1}):
+// Adjoint of one step on a periodic grid (neighbours wrap through the
+// boundary remap of Inst), per cell x (lam = lam^{n+1}):
 //   lam^n(x) = lam(x) + LW^T(lam)(x) - dt (dC/df(x))^T lam(x)
 // with the collision part from cell_adjoint (mrt_dual.h).  Partial sums of
 // the rate gradient per work item go to `partial` (16 doubles per item),
@@ -296,36 +361,41 @@ __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int ite
                                              const S* __restrict__ fn, S* __restrict__ lout,
                                              double* __restrict__ partial) {
     const int lane = lane_id();
-    const unsigned pitch = unsigned(P->pitch);
     const long long plane = P->plane;
     const S* __restrict__ li = lin + P->off;
     const S* __restrict__ fi = fn + P->off;
     S* __restrict__ lo = lout + P->off;
+    const int nx = P->nx;
     const int x = x0 + lane;
-    const bool act = x < P->nx;
+    const bool act = x < nx;
+    const unsigned cx = unsigned(act ? x : P->col_hi);
+    const unsigned xs = unsigned(act ? x : nx + 1);
     const C b = C(P->b);
-    const unsigned hoff = (lane == 0) ? unsigned(-1) : 1u;
+    unsigned hx = cx;
+    if (lane == 0) hx = unsigned(x0 > 0 ? x0 - 1 : P->col_lo);
+    if (lane == 63) hx = unsigned(x0 + 64 < nx ? x0 + 64 : P->col_hi);
     const bool hload = (lane == 0 || lane == 63);
-    auto ldl = [&](int i, unsigned off) -> S { return (li + (long long)i * plane)[off]; };
-    auto ldf = [&](int i, unsigned off) -> S { return (fi + (long long)i * plane)[off]; };
+    // row + col summed in 32 bits, as in the step kernel
+    auto ldl = [&](int i, unsigned row, unsigned col) -> S { return (li + (long long)i * plane)[row + col]; };
+    auto ldf = [&](int i, unsigned row, unsigned col) -> S { return (fi + (long long)i * plane)[row + col]; };
     double acc[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-    unsigned o = unsigned(P->origin) + unsigned(y0) * pitch + unsigned(x);
-    for (int y = y0; y < y1; ++y, o += pitch) {
+    for (int y = y0; y < y1; ++y) {
+        const unsigned o = row_offset(P, y), om = row_offset(P, y - 1), op = row_offset(P, y + 1);
         S l0[16], lm[16], lp[16], fc[16], h[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            l0[i] = ldl(i, o);
-            fc[i] = ldf(i, o);
-            lm[i] = moves_y(i) ? ldl(i, o - pitch) : S(0);
-            lp[i] = moves_y(i) ? ldl(i, o + pitch) : S(0);
+            l0[i] = ldl(i, o, cx);
+            fc[i] = ldf(i, o, cx);
+            lm[i] = moves_y(i) ? ldl(i, om, cx) : S(0);
+            lp[i] = moves_y(i) ? ldl(i, op, cx) : S(0);
             h[i] = S(0);
         }
         if (hload) {
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                if (moves_x(i)) h[i] = ldl(i, o + hoff);
+                if (moves_x(i)) h[i] = ldl(i, o, hx);
         }
         C f[16], lam[16], coll[16], dsk[16];
 #pragma unroll
@@ -356,8 +426,7 @@ __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int ite
                 const S n = lp[i] - l0[i], s = lm[i] - l0[i];
                 d += sy > 0 ? (wd * s + wu * n) : (wu * s + wd * n);
             }
-            const S out = l0[i] + (d - S(coll[i]));
-            if (act) (lo + (long long)i * plane)[o] = out;
+            (lo + (long long)i * plane)[o + xs] = l0[i] + (d - S(coll[i]));
         }
     }
     // wave reduction of the 12 non-trivial rate gradients
@@ -381,12 +450,12 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const Inst* __restrict__ i
                                                       const S* __restrict__ fn,
                                                       S* __restrict__ lout,
                                                       double* __restrict__ partial) {
-    const int wpb = blockDim.x >> 6;
-    int w = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + (threadIdx.x >> 6));
-    const int nw = gridDim.x * wpb;
-    for (; w < nitems; w += nw) {
+    // one block per 256-column item; wave w takes columns x0 + 64 w
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
         const Item it = items[w];
-        adjoint_item<S, C>(insts + it.inst, w, it.x0, it.y0, it.y1, lin, fn, lout, partial);
+        adjoint_item<S, C>(insts + it.inst, w * kWaves + wv, it.x0 + 64 * wv, it.y0, it.y1, lin,
+                           fn, lout, partial);
     }
 }
 
@@ -541,7 +610,7 @@ template <typename S, typename C, bool COMP>
 hipError_t launch_step(const Inst* insts, const Item* items, int nitems, const void* fin,
                        void* fout, unsigned* health, int grid, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    const int blocks = grid > 0 ? grid : (nitems + 3) / 4;
+    const int blocks = grid > 0 ? grid : 8 * ((nitems + 7) / 8);
     hipLaunchKernelGGL((step_kernel<S, C, COMP>), dim3(blocks), dim3(256), 0, st, insts, items,
                        nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
     return hipGetLastError();
@@ -558,15 +627,16 @@ static int grid_for(long long n) {
     return int(g < 65536 ? (g > 0 ? g : 1) : 65536);
 }
 
-// Ghost ring of `count` instances (instance table `insts`, longest
-// perimeter 2 * (nx + ny) = perim) in buffer f.
-hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, bool force_periodic,
+// Ghost cells of `count` instances (instance table `insts`, longest
+// perimeter 2 * (nx + ny) = perim) in buffer f; mode bit 0: reflecting
+// sides, bit 1: fixed-equilibrium sides.
+hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, int mode,
                    hipStream_t st) {
     const dim3 grid((perim + 255) / 256, count);
     switch (prec) {
-        case 0: hipLaunchKernelGGL((ghost_kernel<double, double>), grid, dim3(256), 0, st, insts, static_cast<double*>(f), int(force_periodic)); break;
-        case 1: hipLaunchKernelGGL((ghost_kernel<float, float>), grid, dim3(256), 0, st, insts, static_cast<float*>(f), int(force_periodic)); break;
-        default: hipLaunchKernelGGL((ghost_kernel<float, double>), grid, dim3(256), 0, st, insts, static_cast<float*>(f), int(force_periodic)); break;
+        case 0: hipLaunchKernelGGL((ghost_kernel<double, double>), grid, dim3(256), 0, st, insts, static_cast<double*>(f), mode); break;
+        case 1: hipLaunchKernelGGL((ghost_kernel<float, float>), grid, dim3(256), 0, st, insts, static_cast<float*>(f), mode); break;
+        default: hipLaunchKernelGGL((ghost_kernel<float, double>), grid, dim3(256), 0, st, insts, static_cast<float*>(f), mode); break;
     }
     return hipGetLastError();
 }
@@ -583,7 +653,7 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
                      const void* fn, void* lout, double* partial, double* ds, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    const int blocks = (nitems + 3) / 4;
+    const int blocks = nitems;
     switch (prec) {
         case 0:
             hipLaunchKernelGGL((adjoint_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
@@ -603,7 +673,7 @@ hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, partial, nitems, ds);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, partial, nitems * kWaves, ds);
     return hipGetLastError();
 }
 
