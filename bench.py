@@ -40,12 +40,14 @@ def _events_time(stream, fn, nsteps):
     return e0.elapsed_time(e1) / 1e3
 
 
-def time_solver(case, precision, steps, warmup, autotune=True):
+def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0):
     import torch
 
     from paper_1004_5442_amd.solver import solver_for_case
     s = solver_for_case(case, precision)
-    if autotune:
+    if tile_rows:
+        s.set_tile(tile_rows)
+    elif autotune:
         s.autotune(4)
     s.step(warmup)
     s.sync()
@@ -179,6 +181,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile-rows", type=int, default=0,
+                    help="rows per work item of the headline run (0: autotune)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -201,7 +205,8 @@ def main():
     n = 4096
     head = W.shock_bubble(n=n)
     prec = "fp32_eq64"
-    r = time_solver(head, prec, args.steps, args.warmup, autotune=not args.no_autotune)
+    r = time_solver(head, prec, args.steps, args.warmup, autotune=not args.no_autotune,
+                    tile_rows=args.tile_rows)
     r["steps"] = args.steps
     out = {
         "metric": "MLUPS (million lattice-site updates per second) of the MRT FD-LB step",
