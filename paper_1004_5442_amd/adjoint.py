@@ -60,19 +60,22 @@ class DensityMap(torch.autograd.Function):
         solver.density_adjoint(g_rhoN.detach().to(torch.float64).contiguous(), lam)
         ds = torch.zeros(16, dtype=torch.float64, device=rho0d.device)
         nseg = len(ctx.checkpoints)
+        # one segment's states f^{start+1} .. f^{stop-1}, allocated once and
+        # overwritten by every segment's recomputation
+        pool = [solver.empty_state() for _ in range(K - 1)]
         for seg in range(nseg - 1, -1, -1):
             start = seg * K
             stop = min(N, start + K)
             # recompute f^start .. f^{stop-1}
             states = [ctx.checkpoints[seg]]
             for n in range(start, stop - 1):
-                nxt = solver.empty_state()
+                nxt = pool[n - start]
                 solver.step_buffers(states[-1], nxt)
                 states.append(nxt)
             for n in range(stop - 1, start - 1, -1):
                 solver.adjoint_step(lam, states[n - start], lam2, ds)
                 lam, lam2 = lam2, lam
-            del states
+        del pool
         zero = torch.zeros_like(rho0d)
         g_rho, g_T = torch.empty_like(rho0d), torch.empty_like(rho0d)
         solver.init_adjoint(lam, rho0d, zero, zero, T0d, g_rho=g_rho, g_T=g_T)

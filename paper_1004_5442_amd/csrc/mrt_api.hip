@@ -22,7 +22,7 @@ namespace mrt {
 hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, int mode,
                    hipStream_t st);
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                  void* fout, unsigned* health, int grid, hipStream_t st);
+                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
                      const void* fn, void* lout, double* partial, double* ds, hipStream_t st);
 hipError_t k_init(int prec, const Inst* P, long long cells, const double* rho, const double* ux,
@@ -135,18 +135,22 @@ bool has_kind(const int bc[4], int kind) {
     return false;
 }
 
-// Work items of one instance: 256-column chunks x bands of `rows` rows.
+// Work items of one instance: 256-column chunks x ceil(ny / rows) bands of
+// nearly equal height (at most `rows` rows, heights differ by at most 1).
 void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
-    for (int y0 = 0; y0 < ny; y0 += rows)
-        for (int x0 = 0; x0 < nx; x0 += 256)
-            items.push_back(Item{inst, x0, y0, std::min(ny, y0 + rows)});
+    const long long nb = (ny + rows - 1) / rows;
+    for (long long k = 0; k < nb; ++k) {
+        const int y0 = int(k * ny / nb), y1 = int((k + 1) * ny / nb);
+        for (int x0 = 0; x0 < nx; x0 += 256) items.push_back(Item{inst, x0, y0, y1});
+    }
 }
 
-// enough items for ~2048 blocks (8192 waves) when the grid allows it
+// enough items for ~2048 blocks (8192 waves) when the grid allows it (down
+// to one-row bands on small grids)
 int default_rows(int nx, int ny) {
     const long long chunks = (nx + 255) / 256;
     long long r = (chunks * ny + 2047) / 2048;
-    r = std::max<long long>(4, std::min<long long>(r, 256));
+    r = std::max<long long>(1, std::min<long long>(r, 256));
     return int(std::min<long long>(r, ny));
 }
 
@@ -173,8 +177,11 @@ struct mrt_ctx {
     Inst* d_inst = nullptr;
     Item* d_items = nullptr;
     int nitems = 0, rows = 0, grid = 0;
+    bool nt = false;                 // non-temporal population stores (large grids)
+    Item* d_items_adj = nullptr;     // work items of the adjoint kernel (finer bands)
+    int nitems_adj = 0;
     double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
-    double* d_partial = nullptr;     // 16 doubles per wave of a work item: adjoint partial sums
+    double* d_partial = nullptr;     // 16 doubles per wave of an adjoint item: partial sums
     unsigned* d_health = nullptr;
     bool params_set = false, fields_set = false;
     std::string err;
@@ -202,16 +209,35 @@ int build_items(mrt_ctx* c, int rows) {
     std::vector<Item> items;
     add_items(items, 0, c->nx, c->ny, rows);
     if (c->d_items) HIPTRY(hipFree(c->d_items));
-    if (c->d_partial) HIPTRY(hipFree(c->d_partial));
     c->d_items = nullptr;
-    c->d_partial = nullptr;
     HIPTRY(hipMalloc(&c->d_items, items.size() * sizeof(Item)));
     HIPTRY(hipMemcpy(c->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
-    HIPTRY(hipMalloc(&c->d_partial, items.size() * 4 * 16 * sizeof(double)));
     c->nitems = int(items.size());
     c->rows = rows;
     return MRT_OK;
 }
+
+// Work items of the adjoint kernel.  It keeps no register window across rows
+// (each row loads its own neighbours), so its bands are as short as it takes
+// to give ~1024 blocks (4096 waves), down to one row: a small grid then still
+// spreads over the whole chip.
+int build_adjoint_items(mrt_ctx* c) {
+    std::string& ctx_err = c->err;
+    const long long chunks = (c->nx + 255) / 256;
+    const int rows = int(std::max<long long>(1, std::min<long long>(64, (chunks * c->ny + 1023) / 1024)));
+    std::vector<Item> items;
+    add_items(items, 0, c->nx, c->ny, std::min(rows, c->ny));
+    HIPTRY(hipMalloc(&c->d_items_adj, items.size() * sizeof(Item)));
+    HIPTRY(hipMemcpy(c->d_items_adj, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    HIPTRY(hipMalloc(&c->d_partial, items.size() * 4 * 16 * sizeof(double)));
+    c->nitems_adj = int(items.size());
+    return MRT_OK;
+}
+
+// Stores bypass the caches (non-temporal) once one population buffer is
+// larger than the 256 MB last-level cache: nothing of the new state can stay
+// cached until the next step anyway.  Smaller grids keep it cached.
+constexpr long long kNonTemporalBytes = 256LL << 20;
 
 int check_health(mrt_ctx* c) {
     std::string& ctx_err = c->err;
@@ -283,6 +309,8 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     c->inst.item0 = 0;
     for (int k = 0; k < 4; ++k) c->inst.bc[k] = bc[k];
     if (build_items(c, default_rows(nx, ny)) != MRT_OK) return fail(MRT_EDEVICE);
+    if (build_adjoint_items(c) != MRT_OK) return fail(MRT_EDEVICE);
+    c->nt = (long long)bytes > kNonTemporalBytes;
     (void)ctx_err;
     *out = c;
     return MRT_OK;
@@ -350,7 +378,7 @@ int mrt_step(mrt_ctx* c, int n) {
     for (int k = 0; k < n; ++k) {
         if (reflect) HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[c->cur], 1, c->stream));
         HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[c->cur], c->f[1 - c->cur],
-                           c->d_health, c->grid, c->stream));
+                           c->d_health, c->grid, c->nt, c->stream));
         c->cur ^= 1;
     }
     return MRT_OK;
@@ -365,7 +393,7 @@ int mrt_step_buffers(mrt_ctx* c, const void* fin, void* fout) {
         HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(fin), 3,
                             c->stream));
     HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, fin, fout, c->d_health, c->grid,
-                       c->stream));
+                       c->nt, c->stream));
     return MRT_OK;
 }
 
@@ -470,7 +498,7 @@ int mrt_autotune(mrt_ctx* c, int steps) {
     int dev = 0, cus = 0;
     HIPTRY(hipGetDevice(&dev));
     HIPTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int row_opts[] = {4, 8, 16, 32, 64, 128, 256};
+    const int row_opts[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
     const int grid_mult[] = {0, 2, 4, 8};
     float best = 1e30f;
     int best_rows = c->rows, best_grid = c->grid;
@@ -517,6 +545,7 @@ void mrt_destroy(mrt_ctx* c) {
     }
     if (c->d_inst) (void)hipFree(c->d_inst);
     if (c->d_items) (void)hipFree(c->d_items);
+    if (c->d_items_adj) (void)hipFree(c->d_items_adj);
     if (c->d_stage) (void)hipFree(c->d_stage);
     if (c->d_partial) (void)hipFree(c->d_partial);
     if (c->d_health) (void)hipFree(c->d_health);
@@ -540,7 +569,7 @@ int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* la
     if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
     if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
         return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
-    HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items, c->nitems, lam_next, f_n, lam_n,
+    HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, lam_next, f_n, lam_n,
                           c->d_partial, ds, c->stream));
     return MRT_OK;
 }
@@ -600,6 +629,7 @@ struct mrt_batch {
     Inst* d_insts = nullptr;
     Item* d_items = nullptr;
     int nitems = 0, rows = 0, grid = 0;
+    bool nt = false;                        // non-temporal population stores
     double* d_stage = nullptr;
     unsigned* d_health = nullptr;
     std::map<int, hipGraphExec_t> graphs;   // n steps -> captured launches
@@ -673,6 +703,7 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
     }
     b->total_elems = off;
     const size_t bytes = size_t(off) * elem_size(precision);
+    b->nt = (long long)bytes > kNonTemporalBytes;
     auto fail = [&](int code) {
         mrt_batch_destroy(b);
         return code;
@@ -736,7 +767,7 @@ int mrt_batch_step(mrt_batch* b, int n) {
             if (b->any_reflect) e = mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[c], 1, cap);
             if (e == hipSuccess)
                 e = mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[c], b->f[1 - c],
-                                b->d_health, b->grid, cap);
+                                b->d_health, b->grid, b->nt, cap);
             if (e != hipSuccess) {
                 hipGraph_t g;
                 (void)hipStreamEndCapture(cap, &g);

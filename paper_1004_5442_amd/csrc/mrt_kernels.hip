@@ -5,18 +5,21 @@
 //   f_i(x)^{n+1} = f_i(x) - dt C_i(f(x)) + LW_i(f)(x)
 //   C = Minv diag(s) (M f - fhat^eq(rho, j, e))        (Appendix for M, fhat^eq)
 //   LW_i = sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x))
-// is done by ONE fused kernel per step (step_kernel): each wave owns 64
-// consecutive columns of a band of rows and marches up the band, keeping the
-// rows y-1, y, y+1 of the 16 populations in registers; x neighbours come from
-// the adjacent lanes by DPP wavefront shifts, the two halo columns by a load
-// on lanes 0 and 63; the collision runs in registers in the factored
+// is done by ONE fused kernel per step (step_kernel): a block of four waves
+// owns 256 consecutive columns of a band of rows and marches up the band,
+// keeping the rows y-1, y, y+1 of the 16 populations in registers; x
+// neighbours come from the adjacent lanes by DPP wavefront shifts and from
+// the neighbouring waves through LDS, the two halo columns of the block by a
+// load on one lane each; the collision runs in registers in the factored
 // moment space of mrt_transform.h.  Every population is read from HBM once
-// and written once per step (SoA planes, 256-byte rows per wave, coalesced).
+// (plus the halo rows of each band) and written once per step (SoA planes,
+// 256-byte rows per wave, coalesced).
 //
-// Boundary ghosts (MRT_BC_*) are produced in the same pass: periodic sides
-// load the wrapped row/column, EQ sides use precomputed equilibria, outflow
-// sides copy the boundary cell, reflecting sides evaluate the equilibrium of
-// the boundary cell's moments with the normal momentum reversed.
+// Boundaries (MRT_BC_*): periodic and outflow sides are read through an index
+// remap (the wrapped or the adjacent row/column), fixed-equilibrium sides
+// from a ghost ring written once per buffer, reflecting sides from a ghost
+// ring that ghost_kernel rewrites before each step (the equilibrium of the
+// adjacent cell's moments with the normal momentum reversed).
 #include <hip/hip_runtime.h>
 
 #include "mrt_dual.h"
@@ -206,7 +209,7 @@ struct EdgeBuf {
 // index of an x-moving population among the 12 (0, 2, 4, 6, 8..15)
 constexpr int xslot(int i) { return i < 8 ? i >> 1 : i - 4; }
 
-template <typename S, typename C, bool COMP>
+template <typename S, typename C, bool COMP, bool NT>
 __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, int y0, int y1,
                                            const S* __restrict__ fin, S* __restrict__ fout,
                                            unsigned* __restrict__ health, EdgeBuf<S>& lds) {
@@ -294,7 +297,16 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
                 const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
                 d += wn * rp[i] + (ws * rm[i] - (wd + wu) * r0[i]);
             }
-            (fo + (long long)i * plane)[o + xs] = r0[i] + (d - cdt[i]);
+            // NT (grids far larger than the last-level cache): non-temporal
+            // stores, so the new rows do not displace the halo rows that
+            // other blocks still read; smaller grids keep them cached for
+            // the next step
+            S* dst = &(fo + (long long)i * plane)[o + xs];
+            const S v = r0[i] + (d - cdt[i]);
+            if constexpr (NT)
+                __builtin_nontemporal_store(v, dst);
+            else
+                *dst = v;
         }
         // hand row y+1's edge values to the neighbour waves
         if (more) publish(rp, (y + 1) & 1);
@@ -326,7 +338,7 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
     }
 }
 
-template <typename S, typename C, bool COMP>
+template <typename S, typename C, bool COMP, bool NT>
 __global__ __launch_bounds__(256) void step_kernel(const Inst* __restrict__ insts,
                                                    const Item* __restrict__ items, int nitems,
                                                    const S* __restrict__ fin, S* __restrict__ fout,
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(256) void step_kernel(const Inst* __restrict__ inst
         const int w = (q & 7) * per + (q >> 3);
         if (w >= nitems) continue;
         const Item it = items[w];
-        step_block<S, C, COMP>(insts + it.inst, it.x0, it.y0, it.y1, fin, fout, health, lds);
+        step_block<S, C, COMP, NT>(insts + it.inst, it.x0, it.y0, it.y1, fin, fout, health, lds);
         __syncthreads();   // the next item reuses the edge buffer
     }
 }
@@ -459,22 +471,24 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const Inst* __restrict__ i
     }
 }
 
-// ds[k] += sum over items of partial[item][k], one block, fixed order.
-__global__ __launch_bounds__(256) void reduce_partials(const double* __restrict__ partial,
-                                                       int nitems, double* __restrict__ ds) {
-    __shared__ double red[256];
-    const int t = threadIdx.x;
-    for (int k = 0; k < 16; ++k) {
-        double v = 0.0;
-        for (int i = t; i < nitems; i += 256) v += partial[(long long)i * 16 + k];
-        red[t] = v;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (t < s) red[t] += red[t + s];
-            __syncthreads();
-        }
-        if (t == 0) ds[k] += red[0];
-        __syncthreads();
+// ds[k] += sum over the n partial rows of partial[row][k]: one block of
+// 1024 threads, thread t sums column t % 16 over rows t / 16, t / 16 + 64,
+// ...; the 64 stripe sums are then added in stripe order (a fixed order, so
+// the result is bitwise reproducible).
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void reduce_partials(const double* __restrict__ partial,
+                                                                  int n, double* __restrict__ ds) {
+    constexpr int kStripes = kReduceThreads / 16;
+    __shared__ double red[kStripes][16];
+    const int t = threadIdx.x, k = t & 15, stripe = t >> 4;
+    double v = 0.0;
+    for (int i = stripe; i < n; i += kStripes) v += partial[(long long)i * 16 + k];
+    red[stripe][k] = v;
+    __syncthreads();
+    if (t < 16) {
+        double sum = 0.0;
+        for (int j = 0; j < kStripes; ++j) sum += red[j][t];
+        ds[t] += sum;
     }
 }
 
@@ -608,11 +622,15 @@ __global__ __launch_bounds__(256) void import_kernel(const Inst* __restrict__ P,
 
 template <typename S, typename C, bool COMP>
 hipError_t launch_step(const Inst* insts, const Item* items, int nitems, const void* fin,
-                       void* fout, unsigned* health, int grid, hipStream_t st) {
+                       void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     const int blocks = grid > 0 ? grid : 8 * ((nitems + 7) / 8);
-    hipLaunchKernelGGL((step_kernel<S, C, COMP>), dim3(blocks), dim3(256), 0, st, insts, items,
-                       nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+    if (nt)
+        hipLaunchKernelGGL((step_kernel<S, C, COMP, true>), dim3(blocks), dim3(256), 0, st, insts,
+                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+    else
+        hipLaunchKernelGGL((step_kernel<S, C, COMP, false>), dim3(blocks), dim3(256), 0, st, insts,
+                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
     return hipGetLastError();
 }
 
@@ -642,11 +660,11 @@ hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, i
 }
 
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                  void* fout, unsigned* health, int grid, hipStream_t st) {
+                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
     switch (prec) {
-        case 0: return launch_step<double, double, false>(insts, items, nitems, fin, fout, health, grid, st);
-        case 1: return launch_step<float, float, true>(insts, items, nitems, fin, fout, health, grid, st);
-        default: return launch_step<float, double, false>(insts, items, nitems, fin, fout, health, grid, st);
+        case 0: return launch_step<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        case 1: return launch_step<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        default: return launch_step<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
     }
 }
 
@@ -673,7 +691,7 @@ hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(256), 0, st, partial, nitems * kWaves, ds);
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kReduceThreads), 0, st, partial, nitems * kWaves, ds);
     return hipGetLastError();
 }
 

@@ -1,0 +1,167 @@
+"""GPU parity at full size, in the launch configuration the benchmark times.
+
+The 4096^2 shock-bubble grid (FP32 storage: 1.15 GB per population buffer,
+so the step kernel takes its non-temporal store path) and the 1024^2 2D
+Riemann grid (cache-resident, cached stores) run a few steps on the GPU; the
+oracle evaluates small windows around sampled cells (the shock front, the
+bubble edge, every kind of boundary, the corners) one by one
+(``mrt.evolve_window``: a window of the initial fields grown by one cell per
+step, so every sampled cell's dependence cone is inside it).  A longer run
+checks a property that holds at any size: the shock-bubble problem is
+mirror-symmetric about y = 1/2, so the GPU fields must be too, to rounding.
+"""
+import numpy as np
+import pytest
+
+from helpers import field_errors, fp32_tolerances, oracle_params, oracle_run
+from oracle import mrt
+from paper_1004_5442_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
+
+HEADLINE_TILE_ROWS = 128     # the tile the benchmark runs the 4096^2 grid with
+NSTEPS = 6                   # steps before sampling (window margin = NSTEPS)
+PATCH = 6                    # sampled patch: PATCH x PATCH cells
+
+
+def device_samples(solver, xs, ys):
+    """Populations of the current buffer at cells (xs[k], ys[k]), float64
+    (16, len(xs)); gathers on the device and copies only the samples."""
+    cur, _ = solver.buffers()
+    buf = next(b for b in solver._bufs if b.data_ptr() == cur)
+    flat = buf.view(solver.storage_dtype)
+    xs = torch.as_tensor(np.asarray(xs), dtype=torch.int64, device="cuda")
+    ys = torch.as_tensor(np.asarray(ys), dtype=torch.int64, device="cuda")
+    i = torch.arange(16, dtype=torch.int64, device="cuda")[:, None]
+    idx = i * solver.plane + solver.origin + ys[None, :] * solver.pitch + xs[None, :]
+    return flat[idx].double().cpu().numpy()
+
+
+def patches(case, centres):
+    """(x0, x1, y0, y1) patches of PATCH x PATCH cells around the centres,
+    clipped to the grid."""
+    out = []
+    for cx, cy in centres:
+        x0 = int(np.clip(cx - PATCH // 2, 0, case.nx - PATCH))
+        y0 = int(np.clip(cy - PATCH // 2, 0, case.ny - PATCH))
+        out.append((x0, x0 + PATCH, y0, y0 + PATCH))
+    return out
+
+
+def oracle_patch(case, p, patch, nsteps):
+    x0, x1, y0, y1 = patch
+    f, (wx0, wx1, wy0, wy1) = mrt.evolve_window(case.rho, case.ux, case.uy, case.T, p,
+                                                x0 - nsteps, x1 + nsteps, y0 - nsteps,
+                                                y1 + nsteps, nsteps)
+    sub = f[:, y0 - wy0:y1 - wy0, x0 - wx0:x1 - wx0]
+    assert np.isfinite(sub).all()
+    return sub
+
+
+def compare(case, solver, centres, nsteps, precision):
+    p = oracle_params(case)
+    got_all, want_all = [], []
+    for patch in patches(case, centres):
+        x0, x1, y0, y1 = patch
+        yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        got = device_samples(solver, xx.ravel(), yy.ravel()).reshape(16, PATCH, PATCH)
+        got_all.append(got)
+        want_all.append(oracle_patch(case, p, patch, nsteps))
+    got = np.concatenate(got_all, axis=2)
+    want = np.concatenate(want_all, axis=2)
+    if precision == "fp64":
+        err = np.max(np.abs(got - want)) / np.abs(want).max()
+        print(case.name, precision, "population error", err, flush=True)
+        assert err <= 1e-12
+    else:
+        err = field_errors(mrt.macroscopic(got, p.b), mrt.macroscopic(want, p.b))
+        print(case.name, precision, err, flush=True)
+        assert max(err.values()) < 1e-5, err
+
+
+def shock_bubble_centres(n):
+    sx = int(0.1 * n)                  # shock front
+    bx, by, br = int(0.25 * n), n // 2, int(0.1 * n)
+    # bubble-edge points on the column seams of the 256-column work items
+    seam = 3 * n // 16
+    seam_y = by + int(np.sqrt(br * br - (bx - seam) ** 2))
+    return [(sx, n // 2), (sx, 1), (sx, n - 2),          # shock, where it meets the walls
+            (bx - br, by), (bx + br, by),                # bubble edge
+            (bx, by + br), (bx, by - br), (seam, seam_y),  # bubble edge on item seams
+            (0, n // 3), (n - 1, 2 * n // 3),            # inflow, outflow sides
+            (n // 2, 0), (n // 2, n - 1),                # reflecting walls
+            (0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0)]   # corners
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp64"])
+def test_shock_bubble_4096_sampled(precision):
+    n = 4096
+    case = W.shock_bubble(n=n)
+    print(f"case {case.name} {precision} tile {HEADLINE_TILE_ROWS}", flush=True)
+    s = solver_for_case(case, precision)
+    s.set_tile(HEADLINE_TILE_ROWS)
+    s.step(NSTEPS)
+    s.sync()
+    compare(case, s, shock_bubble_centres(n), NSTEPS, precision)
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp64"])
+def test_riemann2d_1024_sampled_autotuned(precision):
+    n = 1024
+    case = W.riemann2d(n=n, seed=0)
+    print(f"case {case.name} {precision} autotuned", flush=True)
+    s = solver_for_case(case, precision)
+    s.autotune(4)        # restores the initial state
+    s.step(NSTEPS)
+    s.sync()
+    c = n // 2
+    centres = [(c, c), (c - 1, c + 1), (c, 0), (c, n - 1), (0, c), (n - 1, c),
+               (0, 0), (n - 1, n - 1), (255, 700), (768, 300)]
+    compare(case, s, centres, NSTEPS, precision)
+    s.close()
+
+
+def symmetry_tolerances(precision, steps):
+    """FP64: 1e-10 (rounding only).  FP32 storage: the mirror image of a
+    field differs from it by at most twice the field's error, so the
+    tolerance is twice the FP32-storage error, estimated by the oracle with
+    float32-rounded populations on the centre band (4 rows through the
+    bubble, where the shock is one-dimensional), with a further factor 4 for
+    the shock-wall junctions the band does not contain (fp32_tolerances
+    already returns twice the band error)."""
+    if precision == "fp64":
+        return {"rho": 1e-10, "u": 1e-10, "T": 1e-10}
+    band = W.shock_bubble(n=4096, ny=4)
+    want, _ = oracle_run(band, steps)
+    return {k: 4.0 * v for k, v in fp32_tolerances(band, steps, want).items()}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_eq64"])
+def test_shock_bubble_4096_mirror_symmetry(precision):
+    """rho, u_x, T even and u_y odd under y -> 1 - y, after 200 steps."""
+    n, steps = 4096, 200
+    tol = symmetry_tolerances(precision, steps)
+    case = W.shock_bubble(n=n)
+    print(f"case {case.name} {precision} {steps} steps symmetry, tol {tol}", flush=True)
+    s = solver_for_case(case, precision)
+    s.set_tile(HEADLINE_TILE_ROWS)
+    s.step(steps)
+    rho, ux, uy, T = s.moments_device()
+    s.sync()
+    s.close()
+    scale_u = float(torch.sqrt(T.max()))
+    err = {"rho": float((rho - rho.flip(0)).abs().max() / rho.abs().max()),
+           "T": float((T - T.flip(0)).abs().max() / T.abs().max()),
+           "u": max(float((ux - ux.flip(0)).abs().max()),
+                    float((uy + uy.flip(0)).abs().max())) / scale_u}
+    print("symmetry", precision, err, flush=True)
+    assert all(err[k] < tol[k] for k in err), (err, tol)
+    # and the run moved: the shock has advanced several cells
+    assert float(rho[n // 2, int(0.1 * n) + 10]) > 1.5
