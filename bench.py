@@ -29,36 +29,52 @@ HEADLINE_TILE_ROWS = 128            # what the tile autotuner picks for this gri
 
 # HBM traffic of one step_kernel launch on the headline workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean over
-# the dispatches) of
+# the 6 step dispatches) of
 #   bench.py --steps 5 --warmup 1 --no-cpu --no-extra --copy-calibration
-# each scaled by what the counter reads for a plain 1 GiB device copy in the
-# same run (FETCH_SIZE 524,316 KiB -> factor 2.0; WRITE_SIZE 1,048,576 KiB ->
-# factor 1.0).  Valid only for the kernel sources with this digest and this
-# tile height; otherwise the roofline reports traffic = null.
+# each scaled by what the same counter reads, in the same run, for a plain
+# 1 GiB device copy (FETCH_SIZE 524,314.2 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
+# sources with this digest and this tile height; otherwise the roofline
+# reports traffic = null.
 MEASURED_TRAFFIC = {
-    "digest": None,
+    "digest": "37b0e641b95563df3e0ccaabe9dd462643d5274c182130627ceab5b9d2f98fbf",
     "tile_rows": HEADLINE_TILE_ROWS,
-    "fetch_kib": None, "fetch_factor": 2.0,
-    "write_kib": None, "write_factor": 1.0,
+    "fetch_kib": 553697.7, "fetch_copy_kib": 524314.2,
+    "write_kib": 1048576.9, "write_copy_kib": 1048576.0,
 }
-KERNEL_SOURCES = ("mrt_kernels.hip", "mrt_transform.h", "mrt_internal.h", "mrt_dual.h")
+STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
 
 def kernel_digest() -> str:
+    """sha256 over the step kernel's source: mrt_kernels.hip up to the
+    adjoint section (helpers, ghost and step kernels), its launcher, and the
+    headers it includes."""
     import hashlib
+    csrc = os.path.join(ROOT, "paper_1004_5442_amd", "csrc")
+    with open(os.path.join(csrc, "mrt_kernels.hip")) as fh:
+        text = fh.read()
+    head = text[:text.index("// ---------------------------------------------------------------- adjoint")]
+    i0 = text.index("hipError_t launch_step(")
+    launcher = text[i0:text.index("\n}\n", i0)]
     h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1004_5442_amd", "csrc", name), "rb") as fh:
+    for part in (head, launcher):
+        h.update(hashlib.sha256(part.encode()).digest())
+    for name in STEP_HEADERS:
+        with open(os.path.join(csrc, name), "rb") as fh:
             h.update(hashlib.sha256(fh.read()).digest())
     return h.hexdigest()
 
 
 def measured_traffic(precision, tile_rows):
+    """HBM bytes per step-kernel launch (counter readings scaled by the copy
+    calibration), or None when they do not describe the kernel that runs."""
     m = MEASURED_TRAFFIC
-    if (precision != "fp32_eq64" or m["digest"] is None or m["digest"] != kernel_digest()
-            or tile_rows != m["tile_rows"]):
+    if precision != "fp32_eq64" or m["digest"] != kernel_digest() or tile_rows != m["tile_rows"]:
         return None
-    return int(round(m["fetch_kib"] * m["fetch_factor"] * 1024 + m["write_kib"] * m["write_factor"] * 1024))
+    gib_kib = 1024.0 * 1024.0
+    fetch = m["fetch_kib"] * gib_kib / m["fetch_copy_kib"]
+    write = m["write_kib"] * gib_kib / m["write_copy_kib"]
+    return int(round((fetch + write) * 1024))
 
 
 def _events_time(stream, fn, nsteps):
@@ -160,11 +176,15 @@ def time_adjoint(steps):
         density_after(rho0, T0, s0, sv, *args)
     torch.cuda.synchronize()
     t_fwd_full = time.perf_counter() - t0
-    r = rho0.clone().requires_grad_(True)
+    def grad():
+        r = rho0.clone().requires_grad_(True)
+        L = 0.5 * ((density_after(r, T0, s0, sv, *args) - target) ** 2).sum()
+        L.backward()
+        torch.cuda.synchronize()
+
+    grad()          # the first backward also starts autograd's device threads
     t0 = time.perf_counter()
-    L = 0.5 * ((density_after(r, T0, s0, sv, *args) - target) ** 2).sum()
-    L.backward()
-    torch.cuda.synchronize()
+    grad()
     t_grad = time.perf_counter() - t0
     sv.close()
     return {"grid": f"{n}x{n}", "adjoint_step_ms": round(1e3 * t_a, 4), "forward_step_ms": round(1e3 * t_f, 4),

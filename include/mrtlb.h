@@ -165,10 +165,40 @@ const char* mrt_last_error(const mrt_ctx* ctx);
  *            dF/ds_k = -dt Minv[:,k] (fhat_k - fhat^eq_k)      (derived from Eq. 3)
  * lam_next, f_n, lam_n: device buffers in the context's storage precision and
  * padded layout (as mrt_current_buffer).  ds: 16 device doubles, accumulated
- * (the caller zeroes it).  Asynchronous.  lam_n must not alias lam_next; the
- * ghost ring of lam_next is refilled (periodic wrap). */
+ * (the caller zeroes it).  Asynchronous.  lam_n must not alias lam_next;
+ * neighbours across the grid edges are read from the wrapped cells (the ghost
+ * ring is neither read nor written). */
 int mrt_adjoint_step(mrt_ctx* ctx, const void* lam_next, const void* f_n, void* lam_n,
                      double* ds);
+
+/* Forward pass that keeps sqrt(N)-style checkpoints for a later
+ * mrt_adjoint_sweep: for n = 0 .. nsteps-1, copies f^n into
+ * checkpoints[n / segment] when n % segment == 0, then steps (as
+ * mrt_step_buffers).  f: on entry f^0, on return f^nsteps.  f_tmp: one more
+ * state buffer (overwritten).  checkpoints: ceil(nsteps / segment) buffers.
+ * All device buffers in the storage precision and padded layout, owned by the
+ * caller and distinct.  MRT_EINVAL on NULL or aliased buffers, segment < 1 or
+ * nsteps < 0.  Asynchronous. */
+int mrt_step_checkpointed(mrt_ctx* ctx, void* f, void* f_tmp, int segment, int nsteps,
+                          void* const* checkpoints);
+
+/* Backward pass over nsteps steps from the checkpoints written by
+ * mrt_step_checkpointed (same segment): segment by segment, newest first, it
+ * recomputes f^start+1 .. f^stop-1 from checkpoint f^start into `work`, then
+ * runs mrt_adjoint_step for n = stop-1 down to start.  The checkpointing
+ * keeps ceil(N / segment) + segment states for one extra forward step per
+ * step (segment ~ sqrt(N) minimises the memory).
+ *   lam      on entry lam^N, on return lam^0
+ *   lam_tmp  one more buffer (overwritten)
+ *   work     min(segment, nsteps) - 1 state buffers (overwritten)
+ *   ds       16 device doubles, accumulated (the per-cell contributions of
+ *            all steps are summed per wave first and reduced once, so ds
+ *            equals the sum of nsteps mrt_adjoint_step calls up to rounding
+ *            order, and is bitwise reproducible)
+ * Buffers as for mrt_step_checkpointed (the checkpoints are only read).
+ * Periodic grids only (MRT_EINVAL otherwise).  Asynchronous. */
+int mrt_adjoint_sweep(mrt_ctx* ctx, const void* const* checkpoints, int segment, int nsteps,
+                      void* const* work, void* lam, void* lam_tmp, double* ds);
 
 /* One forward step between explicit device buffers (storage precision,
  * padded layout), without touching the context's own buffers: used to

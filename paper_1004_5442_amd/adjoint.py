@@ -8,8 +8,9 @@ Backward: lam^N = g_rho (every population), then per step, newest first,
           (``mrt_adjoint_step``), and finally the adjoint of the
           initialisation gives (d/d rho0, d/d T0) (``mrt_init_adjoint``).
 The states f^n needed by the backward pass are not all kept: every K-th
-state (K ~ sqrt(N)) is stored in the forward pass, and each segment of K
-states is recomputed from its checkpoint just before its adjoint steps, so
+state (K ~ sqrt(N)) is stored in the forward pass (``mrt_step_checkpointed``),
+and each segment of K states is recomputed from its checkpoint just before
+its adjoint steps (``mrt_adjoint_sweep``; both loops run in the library), so
 memory is O(sqrt(N)) states for one extra forward pass.  Periodic grids only.
 """
 from __future__ import annotations
@@ -38,12 +39,8 @@ class DensityMap(torch.autograd.Function):
         zero = torch.zeros_like(rho0d)
         a, b = solver.empty_state(), solver.empty_state()
         solver.init_buffer(rho0d, zero, zero, T0d, a)
-        checkpoints = []
-        for n in range(nsteps):
-            if n % K == 0:
-                checkpoints.append(a.clone())
-            solver.step_buffers(a, b)
-            a, b = b, a
+        checkpoints = [solver.empty_state() for _ in range((nsteps + K - 1) // K)]
+        solver.step_checkpointed(a, b, K, nsteps, checkpoints)
         rhoN = torch.empty_like(rho0d)
         solver.density(a, rhoN)
         ctx.solver, ctx.K, ctx.nsteps = solver, K, nsteps
@@ -59,23 +56,10 @@ class DensityMap(torch.autograd.Function):
         lam, lam2 = solver.empty_state(), solver.empty_state()
         solver.density_adjoint(g_rhoN.detach().to(torch.float64).contiguous(), lam)
         ds = torch.zeros(16, dtype=torch.float64, device=rho0d.device)
-        nseg = len(ctx.checkpoints)
-        # one segment's states f^{start+1} .. f^{stop-1}, allocated once and
-        # overwritten by every segment's recomputation
-        pool = [solver.empty_state() for _ in range(K - 1)]
-        for seg in range(nseg - 1, -1, -1):
-            start = seg * K
-            stop = min(N, start + K)
-            # recompute f^start .. f^{stop-1}
-            states = [ctx.checkpoints[seg]]
-            for n in range(start, stop - 1):
-                nxt = pool[n - start]
-                solver.step_buffers(states[-1], nxt)
-                states.append(nxt)
-            for n in range(stop - 1, start - 1, -1):
-                solver.adjoint_step(lam, states[n - start], lam2, ds)
-                lam, lam2 = lam2, lam
-        del pool
+        # one segment's recomputed states, overwritten by every segment
+        work = [solver.empty_state() for _ in range(min(K, N) - 1)]
+        solver.adjoint_sweep(ctx.checkpoints, K, N, work, lam, lam2, ds)
+        del work
         zero = torch.zeros_like(rho0d)
         g_rho, g_T = torch.empty_like(rho0d), torch.empty_like(rho0d)
         solver.init_adjoint(lam, rho0d, zero, zero, T0d, g_rho=g_rho, g_T=g_T)

@@ -24,7 +24,8 @@ hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, i
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                   void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
-                     const void* fn, void* lout, double* partial, double* ds, hipStream_t st);
+                     const void* fn, void* lout, double* partial, bool accumulate, double* ds,
+                     hipStream_t st);
 hipError_t k_init(int prec, const Inst* P, long long cells, const double* rho, const double* ux,
                   const double* uy, const double* T, void* f, hipStream_t st);
 hipError_t k_moments(int prec, const Inst* P, long long cells, const void* f, double* rho,
@@ -570,7 +571,76 @@ int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* la
     if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
         return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
     HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, lam_next, f_n, lam_n,
-                          c->d_partial, ds, c->stream));
+                          c->d_partial, false, ds, c->stream));
+    return MRT_OK;
+}
+
+int mrt_step_checkpointed(mrt_ctx* c, void* f, void* f_tmp, int segment, int nsteps,
+                          void* const* checkpoints) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    if (!f || !f_tmp || f == f_tmp || segment < 1 || nsteps < 0 || (nsteps > 0 && !checkpoints))
+        return ctx_fail(c, MRT_EINVAL, "bad checkpointed-step arguments");
+    const int nck = (nsteps + segment - 1) / segment;
+    for (int k = 0; k < nck; ++k)
+        if (!checkpoints[k] || checkpoints[k] == f || checkpoints[k] == f_tmp)
+            return ctx_fail(c, MRT_EINVAL, "checkpoint buffers must be distinct from f and f_tmp");
+    const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));
+    void* a = f;
+    void* b = f_tmp;
+    for (int n = 0; n < nsteps; ++n) {
+        if (n % segment == 0)
+            HIPTRY(hipMemcpyAsync(checkpoints[n / segment], a, bytes, hipMemcpyDeviceToDevice, c->stream));
+        const int rc = mrt_step_buffers(c, a, b);
+        if (rc != MRT_OK) return rc;
+        std::swap(a, b);
+    }
+    if (a != f) HIPTRY(hipMemcpyAsync(f, a, bytes, hipMemcpyDeviceToDevice, c->stream));
+    return MRT_OK;
+}
+
+int mrt_adjoint_sweep(mrt_ctx* c, const void* const* checkpoints, int segment, int nsteps,
+                      void* const* work, void* lam, void* lam_tmp, double* ds) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
+    if (!lam || !lam_tmp || lam == lam_tmp || !ds || segment < 1 || nsteps < 0 ||
+        (nsteps > 0 && !checkpoints) || (segment > 1 && nsteps > 1 && !work))
+        return ctx_fail(c, MRT_EINVAL, "bad adjoint-sweep arguments");
+    const int nck = (nsteps + segment - 1) / segment;
+    for (int k = 0; k < nck; ++k)
+        if (!checkpoints[k]) return ctx_fail(c, MRT_EINVAL, "missing checkpoint");
+    const int nwork = std::min(segment, nsteps) - 1;
+    for (int j = 0; j < nwork; ++j)
+        if (!work[j] || work[j] == lam || work[j] == lam_tmp)
+            return ctx_fail(c, MRT_EINVAL, "work buffers must be distinct from lam and lam_tmp");
+    void* cur = lam;
+    void* nxt = lam_tmp;
+    // the rate-gradient partial rows of all steps are summed in place and
+    // reduced into ds once, after the last step
+    bool first = true;
+    for (int seg = nck - 1; seg >= 0; --seg) {
+        const int start = seg * segment, stop = std::min(nsteps, start + segment);
+        // f^{start + j}: the checkpoint for j = 0, else work[j - 1]
+        auto state = [&](int j) -> const void* { return j == 0 ? checkpoints[seg] : work[j - 1]; };
+        for (int j = 1; j < stop - start; ++j) {
+            const int rc = mrt_step_buffers(c, state(j - 1), work[j - 1]);
+            if (rc != MRT_OK) return rc;
+        }
+        for (int n = stop - 1; n >= start; --n) {
+            HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, cur,
+                                  state(n - start), nxt, c->d_partial, !first,
+                                  n == 0 ? ds : nullptr, c->stream));
+            first = false;
+            std::swap(cur, nxt);
+        }
+    }
+    if (cur != lam) {
+        const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));
+        HIPTRY(hipMemcpyAsync(lam, cur, bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
     return MRT_OK;
 }
 

@@ -365,13 +365,14 @@ __global__ __launch_bounds__(256) void step_kernel(const Inst* __restrict__ inst
 // boundary remap of Inst), per cell x (lam = lam^{n+1}):
 //   lam^n(x) = lam(x) + LW^T(lam)(x) - dt (dC/df(x))^T lam(x)
 // with the collision part from cell_adjoint (mrt_dual.h).  Partial sums of
-// the rate gradient per work item go to `partial` (16 doubles per item),
-// reduced in a fixed order by reduce_partials.
+// the rate gradient per wave go to `partial` (16 doubles per wave; with
+// `accumulate` they are added to what the row holds, so a sweep of many
+// steps is reduced once), reduced in a fixed order by reduce_partials.
 template <typename S, typename C>
 __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int item, int x0, int y0,
                                              int y1, const S* __restrict__ lin,
                                              const S* __restrict__ fn, S* __restrict__ lout,
-                                             double* __restrict__ partial) {
+                                             double* __restrict__ partial, bool accumulate) {
     const int lane = lane_id();
     const long long plane = P->plane;
     const S* __restrict__ li = lin + P->off;
@@ -451,7 +452,11 @@ __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int ite
     }
     if (lane == 0) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) partial[(long long)item * 16 + k] = k < 4 ? 0.0 : acc[k];
+        for (int k = 0; k < 16; ++k) {
+            double* dst = &partial[(long long)item * 16 + k];
+            const double v = k < 4 ? 0.0 : acc[k];
+            *dst = accumulate ? *dst + v : v;
+        }
     }
 }
 
@@ -461,13 +466,14 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const Inst* __restrict__ i
                                                       const S* __restrict__ lin,
                                                       const S* __restrict__ fn,
                                                       S* __restrict__ lout,
-                                                      double* __restrict__ partial) {
+                                                      double* __restrict__ partial,
+                                                      int accumulate) {
     // one block per 256-column item; wave w takes columns x0 + 64 w
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
         const Item it = items[w];
         adjoint_item<S, C>(insts + it.inst, w * kWaves + wv, it.x0 + 64 * wv, it.y0, it.y1, lin,
-                           fn, lout, partial);
+                           fn, lout, partial, accumulate != 0);
     }
 }
 
@@ -668,29 +674,35 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
     }
 }
 
+// One adjoint step; partial rows are overwritten (accumulate = false) or
+// added to (true); ds != NULL: then reduce the partial rows into ds.
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
-                     const void* fn, void* lout, double* partial, double* ds, hipStream_t st) {
+                     const void* fn, void* lout, double* partial, bool accumulate, double* ds,
+                     hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    const int blocks = nitems;
+    const int blocks = nitems, acc = accumulate ? 1 : 0;
     switch (prec) {
         case 0:
             hipLaunchKernelGGL((adjoint_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
                                insts, items, nitems, static_cast<const double*>(lin),
-                               static_cast<const double*>(fn), static_cast<double*>(lout), partial);
+                               static_cast<const double*>(fn), static_cast<double*>(lout), partial,
+                               acc);
             break;
         case 1:
             hipLaunchKernelGGL((adjoint_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
                                insts, items, nitems, static_cast<const float*>(lin),
-                               static_cast<const float*>(fn), static_cast<float*>(lout), partial);
+                               static_cast<const float*>(fn), static_cast<float*>(lout), partial,
+                               acc);
             break;
         default:
             hipLaunchKernelGGL((adjoint_kernel<float, double>), dim3(blocks), dim3(256), 0, st,
                                insts, items, nitems, static_cast<const float*>(lin),
-                               static_cast<const float*>(fn), static_cast<float*>(lout), partial);
+                               static_cast<const float*>(fn), static_cast<float*>(lout), partial,
+                               acc);
             break;
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || !ds) return e;
     hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kReduceThreads), 0, st, partial, nitems * kWaves, ds);
     return hipGetLastError();
 }

@@ -153,6 +153,20 @@ class Solver:
     def step_buffers(self, f_in: torch.Tensor, f_out: torch.Tensor):
         self._check(L.raw().mrt_step_buffers(self._h, _dev_ptr(f_in), _dev_ptr(f_out)))
 
+    def step_checkpointed(self, f: torch.Tensor, f_tmp: torch.Tensor, segment: int, nsteps: int,
+                          checkpoints: Sequence[torch.Tensor]):
+        arr = (c_void_p * max(1, len(checkpoints)))(*[t.data_ptr() for t in checkpoints])
+        self._check(L.raw().mrt_step_checkpointed(self._h, _dev_ptr(f), _dev_ptr(f_tmp), int(segment),
+                                                  int(nsteps), arr))
+
+    def adjoint_sweep(self, checkpoints: Sequence[torch.Tensor], segment: int, nsteps: int,
+                      work: Sequence[torch.Tensor], lam: torch.Tensor, lam_tmp: torch.Tensor,
+                      ds: torch.Tensor):
+        ck = (c_void_p * max(1, len(checkpoints)))(*[t.data_ptr() for t in checkpoints])
+        wk = (c_void_p * max(1, len(work)))(*[t.data_ptr() for t in work])
+        self._check(L.raw().mrt_adjoint_sweep(self._h, ck, int(segment), int(nsteps), wk,
+                                              _dev_ptr(lam), _dev_ptr(lam_tmp), _dev_ptr(ds)))
+
     def init_buffer(self, rho, ux, uy, T, f: torch.Tensor):
         self._check(L.raw().mrt_init_buffer(self._h, *[_dev_ptr(t) for t in (rho, ux, uy, T)], _dev_ptr(f)))
 

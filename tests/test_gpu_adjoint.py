@@ -137,3 +137,57 @@ def test_checkpoint_segment_does_not_change_gradient():
         (rhoN ** 2).sum().backward()
         grads.append(r0.grad.cpu().numpy())
     assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[1], grads[2])
+
+
+@pytest.mark.parametrize("nsteps,segment", [(13, 4), (12, 4), (5, 9), (1, 1)])
+def test_native_checkpoint_loops_equal_explicit_steps(nsteps, segment):
+    """mrt_step_checkpointed / mrt_adjoint_sweep against the same work done
+    one mrt_step_buffers / mrt_adjoint_step call at a time (states and lam
+    bitwise, ds to rounding order), for odd and even step counts and a
+    segment longer than the run."""
+    rho, T, s, dt, dx, dy = _small_case(70, 9, seed=2)
+    ny, nx = rho.shape
+    sv = Solver(nx, ny, "fp32_eq64")
+    sv.set_params(1.4, s, dt, dx, dy)
+    r0, T0 = torch.tensor(rho, device="cuda"), torch.tensor(T, device="cuda")
+    zero = torch.zeros_like(r0)
+    # explicit forward: keep every state
+    states = [sv.empty_state()]
+    sv.init_buffer(r0, zero, zero, T0, states[0])
+    for _ in range(nsteps):
+        states.append(sv.empty_state())
+        sv.step_buffers(states[-2], states[-1])
+    # native forward with checkpoints
+    f, tmp = sv.empty_state(), sv.empty_state()
+    sv.init_buffer(r0, zero, zero, T0, f)
+    ck = [sv.empty_state() for _ in range((nsteps + segment - 1) // segment)]
+    sv.step_checkpointed(f, tmp, segment, nsteps, ck)
+    torch.cuda.synchronize()
+    assert torch.equal(_unpadded_t(sv, f), _unpadded_t(sv, states[nsteps]))
+    for k, c in enumerate(ck):
+        assert torch.equal(_unpadded_t(sv, c), _unpadded_t(sv, states[k * segment]))
+    # explicit backward
+    rng = np.random.default_rng(3)
+    lamN = rng.standard_normal((16, ny, nx))
+    lam, lam2 = _padded(sv, lamN), sv.empty_state()
+    ds_ref = torch.zeros(16, dtype=torch.float64, device="cuda")
+    for n in range(nsteps - 1, -1, -1):
+        sv.adjoint_step(lam, states[n], lam2, ds_ref)
+        lam, lam2 = lam2, lam
+    # native sweep
+    lamS, lamT = _padded(sv, lamN), sv.empty_state()
+    work = [sv.empty_state() for _ in range(min(segment, nsteps) - 1)]
+    ds = torch.zeros(16, dtype=torch.float64, device="cuda")
+    sv.adjoint_sweep(ck, segment, nsteps, work, lamS, lamT, ds)
+    torch.cuda.synchronize()
+    assert torch.equal(_unpadded_t(sv, lamS), _unpadded_t(sv, lam))
+    # the sweep sums every step's per-wave partials before one reduction:
+    # the same terms in another order
+    assert torch.allclose(ds, ds_ref, rtol=1e-12, atol=1e-14 * float(ds_ref.abs().max()))
+    sv.close()
+
+
+def _unpadded_t(solver, buf):
+    idx = (np.arange(16)[:, None, None] * solver.plane + solver.origin
+           + np.arange(solver.ny)[None, :, None] * solver.pitch + np.arange(solver.nx)[None, None, :])
+    return buf.view(solver.storage_dtype)[torch.as_tensor(idx.ravel(), device="cuda")]
