@@ -25,30 +25,31 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E, published
 BYTES_PER_SITE = {"fp64": 256, "fp32": 128, "fp32_eq64": 128}   # 16 reads + 16 writes
-HEADLINE_TILE_ROWS = 128            # what the tile autotuner picks for this grid
+HEADLINE_TILE_ROWS = 6              # what the tile autotuner picks for this grid
 
 # HBM traffic of one step_kernel launch on the headline workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean over
 # the 6 step dispatches) of
 #   bench.py --steps 5 --warmup 1 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,314.2 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,314.9 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this tile height; otherwise the roofline
 # reports traffic = null.
 MEASURED_TRAFFIC = {
-    "digest": "37b0e641b95563df3e0ccaabe9dd462643d5274c182130627ceab5b9d2f98fbf",
+    "digest": "49021005b3ee4fda8bbb1f295169ca55a8c9d463decabe74a0360c1b6cdcfb29",
     "tile_rows": HEADLINE_TILE_ROWS,
-    "fetch_kib": 553697.7, "fetch_copy_kib": 524314.2,
-    "write_kib": 1048576.9, "write_copy_kib": 1048576.0,
+    "fetch_kib": 709010.5, "fetch_copy_kib": 524314.9,
+    "write_kib": 1048576.1, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
 
 def kernel_digest() -> str:
-    """sha256 over the step kernel's source: mrt_kernels.hip up to the
-    adjoint section (helpers, ghost and step kernels), its launcher, and the
-    headers it includes."""
+    """sha256 over what decides the step kernel's memory traffic: its source
+    (mrt_kernels.hip up to the adjoint section: helpers, ghost and step
+    kernels), its launcher, the headers it includes, and the population
+    layout (the layout functions of mrt_api.hip)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1004_5442_amd", "csrc")
     with open(os.path.join(csrc, "mrt_kernels.hip")) as fh:
@@ -56,8 +57,11 @@ def kernel_digest() -> str:
     head = text[:text.index("// ---------------------------------------------------------------- adjoint")]
     i0 = text.index("hipError_t launch_step(")
     launcher = text[i0:text.index("\n}\n", i0)]
+    with open(os.path.join(csrc, "mrt_api.hip")) as fh:
+        api = fh.read()
+    layout = api[api.index("// Population layout"):api.index("bool bc_ok(")]
     h = hashlib.sha256()
-    for part in (head, launcher):
+    for part in (head, launcher, layout):
         h.update(hashlib.sha256(part.encode()).digest())
     for name in STEP_HEADERS:
         with open(os.path.join(csrc, name), "rb") as fh:

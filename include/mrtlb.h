@@ -22,11 +22,15 @@
  *    function says it synchronises.  A context is not thread-safe.
  *  - Grid fields are row-major ny x nx arrays (x fastest), cell-centred:
  *    cell (i, j) sits at ((i + 1/2) dx, (j + 1/2) dy).
- *  - Populations are stored structure-of-arrays: plane i (0..15) holds f_i for
- *    every cell, f[i * plane + origin + j * pitch + x], with one ghost cell on
- *    each side (-1 <= x <= nx, -1 <= j <= ny) that the library fills from the
- *    boundary conditions before each step; pitch (a multiple of 64, >= nx + 2),
- *    plane and origin come from mrt_get_layout.  Velocity order: shell 1 (speed 1) and shell 2
+ *  - Populations are stored as rows of 16 population sub-rows: f_i at cell
+ *    (x, j) is element f[i * plane + origin + j * pitch + x] (x fastest, then
+ *    the population, then the row: the 16 populations of one grid row are
+ *    contiguous), with one ghost cell on each side (-1 <= x <= nx,
+ *    -1 <= j <= ny) that the library fills from the boundary conditions as the
+ *    step needs it; plane (the sub-row length, a multiple of 256, >= nx + 3),
+ *    pitch (= 16 plane) and origin come from mrt_get_layout.  Only these
+ *    three numbers describe the layout: code that indexes with them does not
+ *    depend on it.  Velocity order: shell 1 (speed 1) and shell 2
  *    (speed 6) as (+x, +y, -x, -y); shell 3 (sqrt(2)(+-1,+-1)) and shell 4
  *    ((3/sqrt 2)(+-1,+-1)) as (++, -+, --, +-).
  *  - Device pointers are plain HIP device addresses; host pointers are
@@ -97,11 +101,13 @@ typedef struct mrt_params {
 int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
                   void* const f_dev[2], void* stream);
 
-/* Bytes of one population buffer for a grid (16 planes, padded pitch). */
+/* Bytes of one population buffer for a grid (ny + 2 rows of 16 padded
+ * population sub-rows). */
 long long mrt_population_bytes(int nx, int ny, int precision);
 
-/* Row pitch, plane stride and offset of cell (0, 0) in a plane (elements) of
- * the population layout.  Any output may be NULL. */
+/* Row stride (pitch), population stride (plane) and offset of cell (0, 0)
+ * of population 0 (origin), in elements, of the population layout.  Any
+ * output may be NULL. */
 int mrt_get_layout(const mrt_ctx* ctx, long long* pitch, long long* plane, long long* origin);
 
 /* Validate and copy parameters (see mrt_params).  Computes the ghost

@@ -50,16 +50,20 @@ namespace {
 
 size_t elem_size(int prec) { return prec == MRT_FP64 ? 8 : 4; }
 
-// Population layout per plane: rows -1..ny of `pitch` elements (pitch a
-// multiple of 256 >= nx + 3, so every row starts 256-byte aligned, the ghost
-// columns x = -1 / x = nx and the never-read column nx + 1 fit in the row
-// padding, and a 256-column work item never leaves its row), preceded by one
-// 64-element block; cell (0, 0) sits at `origin`.  The plane stride adds an
-// odd number of 64-element blocks so the 16 planes of one row are not a
-// large power of two apart.
-long long pitch_for(int nx) { return ((long long)nx + 3 + 255) / 256 * 256; }
+// Population layout: grid row j (-1..ny, the ghost rows included) is 16
+// consecutive sub-rows, one per population, each `sub` elements long (sub a
+// multiple of 256 >= nx + 3, so every sub-row starts 256-byte aligned, the
+// ghost columns x = -1 / x = nx and the never-read column nx + 1 fit in its
+// padding, and a 256-column work item never leaves it).  Population i of
+// cell (x, j) is at origin + j * pitch + i * plane + x with plane = sub and
+// pitch = 16 sub; 64 elements precede the first sub-row.  A block marching up
+// a band then streams one contiguous 16-sub-row stretch per grid row, which
+// the memory system serves faster than 16 streams a plane apart.
+long long sub_for(int nx) { return ((long long)nx + 3 + 255) / 256 * 256; }
+long long pitch_for(int nx) { return 16 * sub_for(nx); }
+long long plane_for(int nx) { return sub_for(nx); }
 long long origin_for(int nx) { return pitch_for(nx) + 64; }
-long long plane_for(int nx, int ny) { return (long long)(ny + 2) * pitch_for(nx) + 128 + 5 * 64; }
+long long elems_for(int nx, int ny) { return (long long)(ny + 2) * pitch_for(nx) + 512; }
 
 bool bc_ok(const int bc[4]) {
     for (int k = 0; k < 4; ++k)
@@ -146,12 +150,13 @@ void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
     }
 }
 
-// enough items for ~2048 blocks (8192 waves) when the grid allows it (down
-// to one-row bands on small grids)
+// Short bands (at most 6 rows) and many blocks: the step streams best with
+// ~8-16k blocks of short marches (measured on the 4096^2 grid); small grids
+// go down to one-row bands so that they still spread over the chip.
 int default_rows(int nx, int ny) {
     const long long chunks = (nx + 255) / 256;
-    long long r = (chunks * ny + 2047) / 2048;
-    r = std::max<long long>(1, std::min<long long>(r, 256));
+    long long r = (chunks * ny + 8191) / 8192;
+    r = std::max<long long>(1, std::min<long long>(r, 6));
     return int(std::min<long long>(r, ny));
 }
 
@@ -260,7 +265,7 @@ extern "C" {
 
 long long mrt_population_bytes(int nx, int ny, int precision) {
     if (nx < 1 || ny < 1) return 0;
-    return 16LL * plane_for(nx, ny) * (long long)elem_size(precision);
+    return elems_for(nx, ny) * (long long)elem_size(precision);
 }
 
 int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
@@ -276,7 +281,7 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     for (int k = 0; k < 4; ++k) c->bc[k] = bc[k];
     c->stream = static_cast<hipStream_t>(stream);
     c->pitch = pitch_for(nx);
-    c->plane = plane_for(nx, ny);
+    c->plane = plane_for(nx);
     c->origin = origin_for(nx);
     const size_t bytes = size_t(mrt_population_bytes(nx, ny, precision));
     auto fail = [&](int code) {
@@ -499,7 +504,7 @@ int mrt_autotune(mrt_ctx* c, int steps) {
     int dev = 0, cus = 0;
     HIPTRY(hipGetDevice(&dev));
     HIPTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int row_opts[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
+    const int row_opts[] = {1, 2, 3, 4, 5, 6, 8, 12, 16, 32, 64, 128};
     const int grid_mult[] = {0, 2, 4, 8};
     float best = 1e30f;
     int best_rows = c->rows, best_grid = c->grid;
@@ -756,7 +761,7 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
         I.ny = d.ny;
         I.pitch = int(pitch_for(d.nx));
         I.origin = int(origin_for(d.nx));
-        I.plane = plane_for(d.nx, d.ny);
+        I.plane = plane_for(d.nx);
         b->max_perim = std::max(b->max_perim, 2 * (d.nx + d.ny));
         b->any_reflect = b->any_reflect || has_kind(d.bc, MRT_BC_REFLECT);
         I.off = off;
@@ -765,7 +770,7 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
             delete b;
             return MRT_EINVAL;
         }
-        off += 16 * I.plane;
+        off += elems_for(d.nx, d.ny);
         b->cells[i] = (long long)d.nx * d.ny;
         b->total_cells += b->cells[i];
         b->max_cells = std::max(b->max_cells, b->cells[i]);

@@ -13,11 +13,12 @@ enum { BC_PERIODIC = 0, BC_EQ = 1, BC_OUTFLOW = 2, BC_REFLECT = 3 };
 // One grid (instance) as the kernels see it.  Read by every lane of a wave
 // at the same address, so it lives in scalar registers / the scalar cache.
 struct Inst {
-    long long off;      // element offset of population plane 0 in the buffers
-    long long plane;    // elements between population planes
-    int nx, ny, pitch;  // pitch >= nx + 3 and a multiple of 256
-    int origin;         // offset of cell (0, 0) in a plane; cell (x, y) of plane i
-                        // is at off + i * plane + origin + y * pitch + x for
+    long long off;      // element offset of the instance in the buffers
+    long long plane;    // elements between populations (the sub-row length:
+                        // a multiple of 256, >= nx + 3)
+    int nx, ny, pitch;  // pitch: elements between grid rows (16 sub-rows)
+    int origin;         // population i of cell (x, y) is at
+                        // off + i * plane + origin + y * pitch + x for
                         // -1 <= x <= nx, -1 <= y <= ny (x or y outside [0, n):
                         // the ghost ring; column nx + 1 is never read)
     // Where a neighbour outside the grid is read from: column col_lo for

@@ -12,8 +12,9 @@
 // the neighbouring waves through LDS, the two halo columns of the block by a
 // load on one lane each; the collision runs in registers in the factored
 // moment space of mrt_transform.h.  Every population is read from HBM once
-// (plus the halo rows of each band) and written once per step (SoA planes,
-// 256-byte rows per wave, coalesced).
+// (plus the halo rows of each band) and written once per step (256-byte
+// sub-row segments per wave, coalesced; the 16 population sub-rows of a grid
+// row are contiguous).
 //
 // Boundaries (MRT_BC_*): periodic and outflow sides are read through an index
 // remap (the wrapped or the adjacent row/column), fixed-equilibrium sides
@@ -185,8 +186,8 @@ __device__ __forceinline__ unsigned row_offset(const Inst* __restrict__ P, int y
 // ------------------------------------------------------------------- step
 
 // One work item is a block of 4 waves covering 256 columns [x0, x0 + 256)
-// of rows [y0, y1) of one instance (the row pitch is a multiple of 256, so
-// the block never leaves its rows).  Lane l of wave w owns column
+// of rows [y0, y1) of one instance (the sub-row length is a multiple of 256,
+// so the block never leaves its sub-rows).  Lane l of wave w owns column
 // x0 + 64 w + l and the block marches up the band together:
 //  * rows y-1 / y+1 come from a register window (four register sets rotate,
 //    no copies), row y+2 is prefetched while row y is computed;
