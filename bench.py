@@ -308,6 +308,14 @@ def main():
                 "mlups": round(rr["mlups"], 1),
                 "effective_GBs": roofline(rp, pr, rr)["achieved"],
                 "note": "fits the 256 MB Infinity Cache: effective, not HBM, bandwidth"}
+        rm = W.rm_instability()
+        for pr in ("fp32_eq64", "fp64"):
+            rr = time_solver(rm, pr, 4 * k, 64)
+            rr["steps"] = 4 * k
+            extra[f"rm_instability_360x100_{pr}"] = {
+                "mlups": round(rr["mlups"], 1), "ms_per_step": round(rr["ms_per_step"], 5),
+                "tile_rows": rr["tile"][0],
+                "note": "36,000 cells: launch-latency bound (captured graphs of 64 steps)"}
         extra["batched_512_tubes"] = time_batch(max(50, args.steps // 2), 5)
         extra["adjoint_256"] = time_adjoint(100)
         out["extra"] = extra

@@ -140,6 +140,73 @@ bool has_kind(const int bc[4], int kind) {
     return false;
 }
 
+// Captured step launches.  A graph of `steps` steps that starts from buffer
+// `start` (0 or 1) replays the same launches on the same buffers, so n steps
+// run as n / kGraphChunk replays of one kGraphChunk-step graph (an even
+// count: each replay ends on the buffer it started from) and one graph of
+// the n % kGraphChunk remaining steps; graphs are captured on first use and
+// kept until the launch configuration changes.
+constexpr int kGraphChunk = 64;
+
+struct GraphCache {
+    std::map<int, hipGraphExec_t> g;   // key: 2 * steps + start buffer
+    void clear() {
+        for (auto& kv : g) (void)hipGraphExecDestroy(kv.second);
+        g.clear();
+    }
+};
+
+// enqueue(cur, stream) launches one step reading buffer cur.
+template <typename Enqueue>
+hipError_t run_graphs(GraphCache& cache, int& cur, int n, hipStream_t stream, Enqueue enqueue) {
+    auto get = [&](int steps, int start, hipGraphExec_t* out) -> hipError_t {
+        const int key = 2 * steps + start;
+        auto it = cache.g.find(key);
+        if (it != cache.g.end()) {
+            *out = it->second;
+            return hipSuccess;
+        }
+        hipStream_t cap = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            (void)hipStreamDestroy(cap);
+            return e;
+        }
+        int c = start;
+        for (int k = 0; k < steps && e == hipSuccess; ++k) {
+            e = enqueue(c, cap);
+            c ^= 1;
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e_end = hipStreamEndCapture(cap, &graph);
+        if (e == hipSuccess) e = e_end;
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) return e;
+        cache.g.emplace(key, exec);
+        *out = exec;
+        return hipSuccess;
+    };
+    hipGraphExec_t exec = nullptr;
+    for (int q = 0; q < n / kGraphChunk; ++q) {
+        hipError_t e = get(kGraphChunk, cur, &exec);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
+        if (e != hipSuccess) return e;
+    }
+    const int r = n % kGraphChunk;
+    if (r) {
+        hipError_t e = get(r, cur, &exec);
+        if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
+        if (e != hipSuccess) return e;
+        if (r & 1) cur ^= 1;
+    }
+    return hipSuccess;
+}
+
 // Work items of one instance: 256-column chunks x ceil(ny / rows) bands of
 // nearly equal height (at most `rows` rows, heights differ by at most 1).
 void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
@@ -184,6 +251,8 @@ struct mrt_ctx {
     Item* d_items = nullptr;
     int nitems = 0, rows = 0, grid = 0;
     bool nt = false;                 // non-temporal population stores (large grids)
+    GraphCache graphs;               // captured steps of mrt_step
+    bool eager = false;              // launch step by step (the tile autotuner)
     Item* d_items_adj = nullptr;     // work items of the adjoint kernel (finer bands)
     int nitems_adj = 0;
     double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
@@ -220,6 +289,7 @@ int build_items(mrt_ctx* c, int rows) {
     HIPTRY(hipMemcpy(c->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
     c->nitems = int(items.size());
     c->rows = rows;
+    c->graphs.clear();
     return MRT_OK;
 }
 
@@ -381,12 +451,23 @@ int mrt_step(mrt_ctx* c, int n) {
     if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
     const int perim = 2 * (c->nx + c->ny);
     const bool reflect = has_kind(c->bc, MRT_BC_REFLECT);
-    for (int k = 0; k < n; ++k) {
-        if (reflect) HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[c->cur], 1, c->stream));
-        HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[c->cur], c->f[1 - c->cur],
-                           c->d_health, c->grid, c->nt, c->stream));
-        c->cur ^= 1;
+    // one step reading buffer `cur`: reflecting-wall ghosts, then the step
+    auto enqueue = [&](int cur, hipStream_t st) -> hipError_t {
+        if (reflect) {
+            const hipError_t e = mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[cur], 1, st);
+            if (e != hipSuccess) return e;
+        }
+        return mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[cur], c->f[1 - cur],
+                           c->d_health, c->grid, c->nt, st);
+    };
+    if (n == 1 || c->eager) {
+        for (int k = 0; k < n; ++k) {
+            HIPTRY(enqueue(c->cur, c->stream));
+            c->cur ^= 1;
+        }
+        return MRT_OK;
     }
+    HIPTRY(run_graphs(c->graphs, c->cur, n, c->stream, enqueue));
     return MRT_OK;
 }
 
@@ -515,11 +596,13 @@ int mrt_autotune(mrt_ctx* c, int steps) {
             const int g = gm == 0 ? 0 : gm * cus;
             if (g != 0 && g * 4 >= c->nitems) continue;
             c->grid = g;
-            // warm-up, then timed
+            // warm-up, then timed (plain launches: no graph per trial)
+            c->eager = true;
             mrt_step(c, 1);
             HIPTRY(hipEventRecord(e0, c->stream));
             mrt_step(c, steps);
             HIPTRY(hipEventRecord(e1, c->stream));
+            c->eager = false;
             HIPTRY(hipEventSynchronize(e1));
             float ms = 0;
             HIPTRY(hipEventElapsedTime(&ms, e0, e1));
@@ -552,6 +635,7 @@ void mrt_destroy(mrt_ctx* c) {
     if (c->d_inst) (void)hipFree(c->d_inst);
     if (c->d_items) (void)hipFree(c->d_items);
     if (c->d_items_adj) (void)hipFree(c->d_items_adj);
+    c->graphs.clear();
     if (c->d_stage) (void)hipFree(c->d_stage);
     if (c->d_partial) (void)hipFree(c->d_partial);
     if (c->d_health) (void)hipFree(c->d_health);
@@ -707,7 +791,7 @@ struct mrt_batch {
     bool nt = false;                        // non-temporal population stores
     double* d_stage = nullptr;
     unsigned* d_health = nullptr;
-    std::map<int, hipGraphExec_t> graphs;   // n steps -> captured launches
+    GraphCache graphs;                      // captured steps
     std::string err;
 };
 
@@ -726,7 +810,6 @@ int batch_items(mrt_batch* b, int rows) {
     HIPTRY(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
     b->nitems = int(items.size());
     b->rows = rows;
-    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     b->graphs.clear();
     return MRT_OK;
 }
@@ -828,40 +911,15 @@ int mrt_batch_step(mrt_batch* b, int n) {
     if (!b || n < 0) return MRT_EINVAL;
     std::string& ctx_err = b->err;
     if (n == 0) return MRT_OK;
-    // graph of n launches starting from buffer 0; a start from buffer 1 uses
-    // the key -n (the buffers alternate the other way)
-    const int key = b->cur == 0 ? n : -n;
-    auto it = b->graphs.find(key);
-    if (it == b->graphs.end()) {
-        hipStream_t cap = nullptr;
-        HIPTRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        HIPTRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-        int c = b->cur;
-        for (int k = 0; k < n; ++k) {
-            hipError_t e = hipSuccess;
-            if (b->any_reflect) e = mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[c], 1, cap);
-            if (e == hipSuccess)
-                e = mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[c], b->f[1 - c],
-                                b->d_health, b->grid, b->nt, cap);
-            if (e != hipSuccess) {
-                hipGraph_t g;
-                (void)hipStreamEndCapture(cap, &g);
-                (void)hipStreamDestroy(cap);
-                b->err = std::string("capture: ") + hipGetErrorString(e);
-                return MRT_EDEVICE;
-            }
-            c ^= 1;
+    auto enqueue = [&](int cur, hipStream_t st) -> hipError_t {
+        if (b->any_reflect) {
+            const hipError_t e = mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[cur], 1, st);
+            if (e != hipSuccess) return e;
         }
-        hipGraph_t graph = nullptr;
-        HIPTRY(hipStreamEndCapture(cap, &graph));
-        hipGraphExec_t exec = nullptr;
-        HIPTRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        HIPTRY(hipGraphDestroy(graph));
-        HIPTRY(hipStreamDestroy(cap));
-        it = b->graphs.emplace(key, exec).first;
-    }
-    HIPTRY(hipGraphLaunch(it->second, b->stream));
-    if (n & 1) b->cur ^= 1;
+        return mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[cur], b->f[1 - cur],
+                           b->d_health, b->grid, b->nt, st);
+    };
+    HIPTRY(run_graphs(b->graphs, b->cur, n, b->stream, enqueue));
     return MRT_OK;
 }
 
@@ -975,7 +1033,7 @@ long long mrt_batch_cells(const mrt_batch* b) { return b ? b->total_cells : 0; }
 void mrt_batch_destroy(mrt_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
-    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
     if (b->f[0]) (void)hipFree(b->f[0]);
     if (b->f[1]) (void)hipFree(b->f[1]);
     if (b->d_insts) (void)hipFree(b->d_insts);

@@ -262,3 +262,90 @@ def shock_bubble(n: int = 4096, nsteps: int = 5000, T1: float = 0.6, mach: float
                 s=rates(2e5, 2e5, 0.71, 2e5), dt=5e-6, dx=h, dy=h,
                 bc=("eq", "outflow", "reflect", "reflect"),
                 side_state=(post, pre, pre, pre), nsteps=nsteps, meta={"post": post})
+
+
+# ---------------------------------------------------------------------------
+# Richtmyer-Meshkov instability (the paper's section (d))
+# ---------------------------------------------------------------------------
+
+RM_STATES = {   # (rho, ux, uy, p) as the paper prints them
+    "light": (0.1358, 0.0, 0.0, 1.0),
+    "heavy": (1.0, 0.0, 0.0, 1.0),
+    "shocked": (3.33333, -2.07063, 0.0, 7.125),
+}
+
+
+def rm_instability(nx: int = 360, ny: int = 100, nsteps: int = 4000, shock_x: float = 0.25,
+                   width_cells: float = 2.0) -> Case:
+    """Shock-driven Richtmyer-Meshkov instability on [0, 0.36] x [0, 0.1]
+    (360 x 100 cells at the paper's size): light gas (rho 0.1358, p 1) left
+    of the interface x = 0.24 + 0.005 sin(pi/2 + 40 pi y), heavy gas
+    (rho 1, p 1) right of it, and the Mach-2.5 shocked heavy gas
+    (3.33333, -2.07063, 0, p = 7.125) right of a planar shock at x = shock_x
+    (the paper only says that the shock hits the interface at once; 0.25 is
+    five cells right of the interface crests).  gamma = 1.4, dt = 1e-5,
+    s_5 = 2e3 and every other rate 1e5 (so Pr = s_8 / s_6 = 1).  Inflow of
+    the shocked state on the right, a reflecting wall on the left, periodic
+    top and bottom."""
+    lx, ly = 0.36, 0.1
+    dx, dy = lx / nx, ly / ny
+    x = (np.arange(nx) + 0.5) * dx
+    y = (np.arange(ny) + 0.5) * dy
+    Y, X = np.meshgrid(y, x, indexing="ij")
+    prim = {k: (v[0], v[1], v[2], v[3] / v[0]) for k, v in RM_STATES.items()}
+    iface = 0.24 + 0.005 * np.sin(np.pi / 2 + 40.0 * np.pi * Y)
+    h = min(dx, dy)
+    w_heavy = _ramp(X - iface, width_cells, h)             # 0 light, 1 heavy
+    w_shock = _ramp(X - shock_x, width_cells, h)           # 1 behind the shock
+    f = _blend(prim["light"], prim["heavy"], w_heavy)
+    f = _blend(tuple(f), prim["shocked"], w_shock)
+    s = np.zeros(16)
+    s[4] = 2e3
+    s[5:] = 1e5
+    shocked = prim["shocked"]
+    return Case(f"rm_instability_{nx}x{ny}", nx, ny, *[np.asarray(a, dtype=float) for a in f],
+                gamma=1.4, Pr=1.0, s=s, dt=1e-5, dx=dx, dy=dy,
+                bc=("reflect", "eq", "periodic", "periodic"),
+                side_state=(prim["light"], shocked, shocked, shocked), nsteps=nsteps)
+
+
+# ---------------------------------------------------------------------------
+# The paper's strong-shock Riemann problem (section (b)), MRT and SRT
+# ---------------------------------------------------------------------------
+
+STRONG_SHOCK_LEFT: State = (5.99924, 19.5975, 0.0, 76.8254)      # (rho, u1, u2, T)
+STRONG_SHOCK_RIGHT: State = (5.99242, -6.19633, 0.0, 7.69222)
+
+
+def srt_rates(tau: float) -> np.ndarray:
+    """Single-relaxation-time (BGK) limit of the MRT collision: every rate
+    1/tau (s_1..4 multiply collision invariants and are kept at 0)."""
+    s = np.zeros(16)
+    s[4:] = 1.0 / tau
+    return s
+
+
+def strong_shock_tube(gamma: float = 1.4, srt: bool = False, nx: int = 1100, ny: int = 1,
+                      x0: float = 0.25, nsteps: int = 130000, width_cells: float = 0.0) -> Case:
+    """The paper's one-dimensional Riemann problem run with the 2D model:
+    left (5.99924, 19.5975, 0, T = 76.8254), right (5.99242, -6.19633, 0,
+    T = 7.69222), dx = dy = 0.002, dt = 1e-6, t = 0.13 after 130,000 steps.
+    MRT rates s_5 = 5e3, s_6 = 1e4, every other rate 1e5 (so Pr = 10); SRT:
+    tau = 1e-5, every rate 1e5.  The paper gives no domain: [0, 2.2] with the
+    diaphragm at x0 = 0.25 holds every wave up to t = 0.13 for gamma = 7/5
+    and 5/3 with 50 cells to spare at each end, so the fixed-equilibrium ends
+    are never reached, as the paper requires.  y is periodic; one row by
+    default: with several rows the MRT run carries y-waves that are linearly
+    unstable at the hot left state (tests/test_paper_cases.py)."""
+    dx = 0.002
+    x = (np.arange(nx) + 0.5) * dx
+    X = np.broadcast_to(x, (ny, nx))
+    w = _ramp(X - x0, width_cells, dx)
+    f = _blend(STRONG_SHOCK_LEFT, STRONG_SHOCK_RIGHT, w)
+    s = srt_rates(1e-5) if srt else rates(5e3, 1e4, 10.0, 1e5)
+    name = f"strong_shock_{'srt' if srt else 'mrt'}_g{gamma:.4f}_{nx}x{ny}"
+    return Case(name, nx, ny, *[np.ascontiguousarray(a, dtype=float) for a in f],
+                gamma=gamma, Pr=float(s[7] / s[5]), s=s, dt=1e-6, dx=dx, dy=dx,
+                bc=("eq", "eq", "periodic", "periodic"),
+                side_state=(STRONG_SHOCK_LEFT, STRONG_SHOCK_RIGHT, STRONG_SHOCK_LEFT,
+                            STRONG_SHOCK_LEFT), nsteps=nsteps, meta={"x0": x0})

@@ -74,3 +74,21 @@ def fp32_tolerances(case, nsteps, want64, floor=1e-5):
     f32, p = fp32_storage_reference(case, nsteps)
     base = field_errors(mrt.macroscopic(f32, p.b), mrt.macroscopic(want64, p.b))
     return {k: max(floor, 2.0 * v) for k, v in base.items()}
+
+
+def fp64_rounding_spread(case, nsteps, want, seed=0):
+    """How far one-ulp rounding differences move an FP64 run: the oracle
+    rerun with every population multiplied by (1 +- 2^-52) (random sign)
+    after each step, compared with the plain oracle result `want` (relative
+    to the population scale).  Two correct FP64 implementations that order
+    or fuse their operations differently differ by about this much; on
+    well-conditioned cases it is ~1e-14, on the paper's hot supersonic
+    strong-shock states (populations far larger than the density they sum
+    to) ~1e-10 after 2000 steps."""
+    p = oracle_params(case)
+    rng = np.random.default_rng(seed)
+    f = mrt.init_populations(case.rho, case.ux, case.uy, case.T, p)
+    for _ in range(nsteps):
+        f = mrt.step(f, p)
+        f = f * (1.0 + np.ldexp(rng.choice([-1.0, 1.0], size=f.shape), -52))
+    return float(np.max(np.abs(f - want)) / np.abs(want).max())

@@ -1,0 +1,136 @@
+"""The paper's own test problems on the GPU: the Richtmyer-Meshkov
+instability (section (d)) and the strong-shock Riemann problem of section
+(b) in its MRT and SRT forms.
+
+Parity: full-size runs against the FP64 oracle on the same inputs.  Physics:
+the paper's claim that MRT shows weaker oscillations at the discontinuities
+than SRT (section (b)), measured against the exact Riemann solution after
+the paper's 130,000 steps; and the instability of the gamma = 5/3 MRT run,
+which the oracle's linear stability analysis predicts under this build's
+reading of the time and space discretisation.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from helpers import field_errors, fp32_tolerances, fp64_rounding_spread, oracle_run
+from oracle import mrt, riemann
+from paper_1004_5442_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+from paper_1004_5442_amd.lib import UnstableError  # noqa: E402
+from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
+
+RM_STEPS = 150
+
+
+@functools.lru_cache(maxsize=None)
+def _rm_reference():
+    case = W.rm_instability()
+    want, p = oracle_run(case, RM_STEPS)
+    return case, want, p
+
+
+def test_rm_instability_fp64_full_size():
+    case, want, p = _rm_reference()
+    print(f"case {case.name} fp64 {RM_STEPS} steps", flush=True)
+    s = solver_for_case(case, "fp64")
+    s.autotune(4)
+    s.step(RM_STEPS)
+    got = s.populations()
+    s.close()
+    err = np.max(np.abs(got - want)) / np.abs(want).max()
+    print("population error", err)
+    assert err <= 1e-12
+
+
+def test_rm_instability_fp32_eq64_full_size():
+    case, want, p = _rm_reference()
+    print(f"case {case.name} fp32_eq64 {RM_STEPS} steps", flush=True)
+    tol = fp32_tolerances(case, RM_STEPS, want)
+    s = solver_for_case(case, "fp32_eq64")
+    s.autotune(4)
+    s.step(RM_STEPS)
+    err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+    s.close()
+    print("field errors", err, "tolerances", tol)
+    assert all(err[k] < tol[k] for k in err), (err, tol)
+
+
+@pytest.mark.parametrize("gamma,srt", [(1.4, False), (5.0 / 3.0, True)])
+def test_strong_shock_fp64_matches_oracle(gamma, srt):
+    case = W.strong_shock_tube(gamma, srt, ny=1)
+    print(f"case {case.name} fp64 2000 steps", flush=True)
+    want, p = oracle_run(case, 2000)
+    s = solver_for_case(case, "fp64")
+    s.step(2000)
+    got = s.populations()
+    s.close()
+    err = np.max(np.abs(got - want)) / np.abs(want).max()
+    # the hot supersonic states amplify rounding: the bar is 1e-12 or four
+    # times the oracle's own spread under one-ulp perturbations, if larger
+    tol = max(1e-12, 4.0 * fp64_rounding_spread(case, 2000, want))
+    print("population error", err, "tolerance", tol)
+    assert err <= tol
+
+
+def _run_to_end(case):
+    s = solver_for_case(case, "fp64")
+    s.step(case.nsteps)
+    rho = s.moments()[0][0]
+    s.close()
+    return rho
+
+
+def _exact_density(case, gamma, t):
+    L, R = W.STRONG_SHOCK_LEFT, W.STRONG_SHOCK_RIGHT
+    x = (np.arange(case.nx) + 0.5) * case.dx
+    rho, _, _ = riemann.sample((L[0], L[1], L[0] * L[3]), (R[0], R[1], R[0] * R[3]), gamma,
+                               (x - case.meta["x0"]) / t)
+    return rho
+
+
+def test_strong_shock_mrt_oscillates_less_than_srt():
+    """gamma = 7/5, t = 0.13 (130,000 steps, FP64): against the exact
+    solution, the MRT run's density has a smaller L1 error and much less
+    excess total variation (the oscillations at the discontinuities) than
+    the SRT run."""
+    g = 1.4
+    out = {}
+    for srt in (False, True):
+        case = W.strong_shock_tube(g, srt, ny=1)
+        print(f"case {case.name} fp64 {case.nsteps} steps", flush=True)
+        rho = _run_to_end(case)
+        exact = _exact_density(case, g, case.nsteps * case.dt)
+        l1 = float(np.sum(np.abs(rho - exact)) * case.dx)
+        tv_excess = float(np.sum(np.abs(np.diff(rho))) - np.sum(np.abs(np.diff(exact))))
+        mass = float(np.sum(exact) * case.dx)
+        out["srt" if srt else "mrt"] = (l1 / mass, tv_excess)
+    print("relative L1, excess total variation:", out)
+    (l1_m, tv_m), (l1_s, tv_s) = out["mrt"], out["srt"]
+    assert l1_m < 0.03                     # MRT within 3 % of the exact solution
+    assert l1_m < l1_s
+    assert tv_m < 0.5 * tv_s
+
+
+def test_strong_shock_gamma_5_3_mrt_instability_is_detected():
+    """The gamma = 5/3 MRT run is linearly unstable at the hot left state
+    under the unsplit forward-Euler / per-axis Lax-Wendroff reading (its
+    amplification factor exceeds 1 by ~2e-4 per step, tests/test_paper_cases.py):
+    the run stays healthy for 20,000 steps, then the growing mode drives it
+    non-physical before the paper's end time and the library reports it."""
+    case = W.strong_shock_tube(5.0 / 3.0, srt=False, ny=1)
+    print(f"case {case.name} fp64 until unhealthy", flush=True)
+    s = solver_for_case(case, "fp64")
+    s.step(20000)
+    s.sync()                 # healthy so far
+    with pytest.raises(UnstableError):
+        s.step(case.nsteps - 20000)
+        s.sync()
+    s.close()

@@ -103,3 +103,22 @@ def test_bitwise_deterministic():
         s.step(50)
         outs.append(s.populations())
     assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_eq64"])
+def test_graph_replays_equal_plain_launches(precision):
+    """mrt_step(n) for n > 1 replays captured graphs (64-step chunks plus a
+    remainder graph, two start buffers); a twin grid stepped one launch at a
+    time must agree bitwise after every call, with other work in between."""
+    case = smooth_case(300, 40, ("reflect", "eq", "periodic", "periodic"), seed=11)
+    print(f"case {case.name} {precision} graph replays", flush=True)
+    a = solver_for_case(case, precision)    # plain launches
+    b = solver_for_case(case, precision)    # graphs
+    for n in (69, 12, 69, 3, 64):
+        for _ in range(n):
+            a.step(1)
+        b.step(n)
+        pa, pb = a.populations(), b.populations()   # synchronising host work in between
+        assert np.array_equal(pa, pb), n
+    a.close()
+    b.close()

@@ -77,3 +77,58 @@ def test_shock_bubble_layout():
     assert c.rho[128, 2] == pytest.approx(post[0], rel=1e-6)
     assert c.rho[128, 64] == pytest.approx(3.0, rel=1e-6)      # bubble centre (0.25, 0.5)
     assert c.rho[128, 200] == pytest.approx(1.0, rel=1e-6)
+
+
+def test_rm_instability_layout():
+    """Section (d): 360 x 100 cells on 0.36 x 0.1, the three printed states,
+    the interface x = 0.24 + 0.005 sin(pi/2 + 40 pi y) (period 0.05 = 50
+    rows), inflow right, reflecting left, periodic top and bottom."""
+    c = W.rm_instability()
+    assert (c.nx, c.ny) == (360, 100) and c.dx == pytest.approx(0.001) and c.dy == pytest.approx(0.001)
+    assert c.bc == ("reflect", "eq", "periodic", "periodic")
+    _, rh = _golden()
+    mach, rho1, p1, rho2, u2, p2, tol = rh[0]
+    shocked = W.RM_STATES["shocked"]
+    assert shocked == (rho2, u2, 0.0, p2)
+    assert W.RM_STATES["heavy"] == (rho1, 0.0, 0.0, p1)
+    assert c.side_state[1] == pytest.approx((rho2, u2, 0.0, p2 / rho2), rel=1e-15)
+    # far-field states: light gas at the left wall, shocked gas at the inflow
+    assert c.rho[:, 0] == pytest.approx(0.1358) and c.T[:, 0] == pytest.approx(1 / 0.1358)
+    assert c.rho[:, -1] == pytest.approx(rho2) and c.ux[:, -1] == pytest.approx(u2)
+    # heavy gas between interface and shock (widest at the troughs, row 25:
+    # interface 0.235, shock 0.25), at rest, p = 1
+    k = 242
+    # (the two 2-cell ramps overlap slightly there: within 1 %)
+    assert c.rho[25, k] == pytest.approx(1.0, rel=1e-2)
+    assert c.rho[25, k] * c.T[25, k] == pytest.approx(1.0, rel=1e-2)
+    assert abs(c.ux[25, k]) < 1e-2 * abs(u2)
+    # the interface (rho = (0.1358 + 1) / 2; linear interpolation between cell
+    # centres, within 0.15 cells) sits at 0.245 on rows y = 0.0005 and
+    # at 0.235 half a period later, and the field repeats every 50 rows
+    def crossing(row):
+        r = c.rho[row]
+        k = int(np.argmax(r > 0.5 * (0.1358 + 1.0)))
+        return (k - 0.5 + (0.5679 - r[k - 1]) / (r[k] - r[k - 1])) * c.dx
+    y0 = 0.5 * c.dy
+    assert crossing(0) == pytest.approx(0.24 + 0.005 * np.cos(40 * np.pi * y0), abs=1.5e-4)
+    assert crossing(25) == pytest.approx(0.24 + 0.005 * np.cos(40 * np.pi * (25.5 * c.dy)), abs=1.5e-4)
+    assert np.allclose(c.rho[:50], c.rho[50:], rtol=1e-12, atol=0)
+    assert c.s[4] == 2e3 and np.all(c.s[5:] == 1e5) and np.all(c.s[:4] == 0) and c.dt == 1e-5
+
+
+def test_strong_shock_tube_states_and_rates():
+    """Section (b): printed states and parameters; MRT rates s_5 = 5e3,
+    s_6 = 1e4, others 1e5; SRT tau = 1e-5 (all rates 1e5); the pressures
+    rho T are Toro's test-5 values."""
+    m = W.strong_shock_tube(1.4, srt=False, ny=1)
+    s = W.strong_shock_tube(5 / 3, srt=True, ny=1)
+    assert m.dx == 0.002 and m.dt == 1e-6 and m.nsteps == 130000
+    assert m.s[4] == 5e3 and m.s[5] == m.s[6] == 1e4 and np.all(m.s[7:] == 1e5)
+    assert np.allclose(s.s[4:], 1e5, rtol=1e-15) and np.all(s.s[:4] == 0)
+    L, R = W.STRONG_SHOCK_LEFT, W.STRONG_SHOCK_RIGHT
+    assert L[0] * L[3] == pytest.approx(460.894, rel=2e-6)
+    assert R[0] * R[3] == pytest.approx(46.0950, rel=2e-6)
+    x0 = m.meta["x0"]
+    xc = (np.arange(m.nx) + 0.5) * m.dx
+    assert np.all(m.rho[0][xc < x0] == L[0]) and np.all(m.rho[0][xc > x0] == R[0])
+    assert m.bc == ("eq", "eq", "periodic", "periodic")
