@@ -114,7 +114,7 @@ def test_strong_shock_mrt_oscillates_less_than_srt():
         out["srt" if srt else "mrt"] = (l1 / mass, tv_excess)
     print("relative L1, excess total variation:", out)
     (l1_m, tv_m), (l1_s, tv_s) = out["mrt"], out["srt"]
-    assert l1_m < 0.03                     # MRT within 3 % of the exact solution
+    assert l1_m < 0.02                     # MRT within 2 % of the exact solution (0.94 %)
     assert l1_m < l1_s
     assert tv_m < 0.5 * tv_s
 
