@@ -29,6 +29,10 @@ them with reasons):
 * time advance: unsplit forward Euler, collision and convection both from f^n;
 * 2D Lax-Wendroff: the 1D Lax-Wendroff difference applied per axis and summed
   (five-point stencil);
+* the two alternative readings of that passage, as options of Params: the
+  collide-then-stream split (convection of the post-collision populations,
+  ``split``) and the full 2D Lax-Wendroff stencil with the mixed-derivative
+  term (nine points, ``lw_cross``);
 * grid: cell-centred with one ghost layer per side; "f_i = f_i^eq on the
   boundary nodes" fills the ghost layer;
 * reflecting wall: ghost = f^eq(rho, mirrored velocity, T) of the mirror-image
@@ -185,6 +189,8 @@ class Params:
     eta0: float = 2.5
     bc: Sequence[int] = (BC_PERIODIC, BC_PERIODIC, BC_PERIODIC, BC_PERIODIC)
     side_state: Sequence[Sequence[float]] = ((1.0, 0.0, 0.0, 1.0),) * 4
+    split: bool = False      # collide, then convect the post-collision populations
+    lw_cross: bool = False   # add the mixed-derivative term of 2D Lax-Wendroff
 
     @property
     def b(self) -> float:
@@ -260,7 +266,10 @@ def _reflected_eq(f_cells, normal_axis: str, p: Params):
 def fill_ghosts(f, p: Params):
     """Return f padded with one ghost layer, shape (16, ny+2, nx+2).
 
-    Corner ghosts are never read by the five-point stencil and stay NaN.
+    The x sides are filled first (rows 1..ny); the y sides are then filled
+    over the whole padded width, so a corner ghost is the y side's rule
+    applied to the x-side ghost next to it.  Only the nine-point stencil
+    (lw_cross) reads corners.
     """
     n, ny, nx = f.shape
     g = np.full((n, ny + 2, nx + 2), np.nan, dtype=np.result_type(f.dtype, np.float64))
@@ -288,18 +297,19 @@ def fill_ghosts(f, p: Params):
         else:
             raise ValueError(f"unknown boundary kind {kind}")
 
-    # y sides: ghost rows 0 and ny+1, columns 1..nx
+    # y sides: ghost rows 0 and ny+1, all nx+2 columns (padded rows irow + 1
+    # and wrow + 1 already hold their x ghosts)
     for side, grow, irow, wrow in ((YLO, 0, 0, ny - 1), (YHI, ny + 1, ny - 1, 0)):
         kind = bc[side]
         if kind == BC_PERIODIC:
-            g[:, grow, 1:-1] = f[:, wrow, :]
+            g[:, grow, :] = g[:, wrow + 1, :]
         elif kind == BC_EQ:
             r, u, v, t = p.side_state[side]
-            g[:, grow, 1:-1] = feq(r, u, v, t, p.b, p.eta0)[:, None]
+            g[:, grow, :] = feq(r, u, v, t, p.b, p.eta0)[:, None]
         elif kind == BC_OUTFLOW:
-            g[:, grow, 1:-1] = f[:, irow, :]
+            g[:, grow, :] = g[:, irow + 1, :]
         elif kind == BC_REFLECT:
-            g[:, grow, 1:-1] = _reflected_eq(f[:, irow, :], "y", p)
+            g[:, grow, :] = _reflected_eq(g[:, irow + 1, :], "y", p)
         elif kind == BC_NONE:
             pass
         else:
@@ -325,7 +335,10 @@ def lax_wendroff(g, p: Params):
     For one axis with Courant number c the 1D Lax-Wendroff update of
     df/dt + v df/dx = 0 is
         -c/2 (f[x+1] - f[x-1]) + c^2/2 (f[x+1] - 2 f[x] + f[x-1]);
-    the two axes are summed.
+    the two axes are summed.  With p.lw_cross the second-order Taylor term
+    dt^2 v_x v_y d2f/dxdy of the 2D scheme is added, with the central
+    difference d2f/dxdy = (f[x+1,y+1] - f[x-1,y+1] - f[x+1,y-1] + f[x-1,y-1])
+    / (4 dx dy): the increment (c_x c_y / 4) (NE - NW - SE + SW).
     """
     cx, cy = courant_numbers(p)
     c = g[:, 1:-1, 1:-1]
@@ -333,8 +346,13 @@ def lax_wendroff(g, p: Params):
     west = g[:, 1:-1, :-2]
     north = g[:, 2:, 1:-1]
     south = g[:, :-2, 1:-1]
-    return (-0.5 * cx * (east - west) + 0.5 * cx * cx * (east - 2.0 * c + west)
-            - 0.5 * cy * (north - south) + 0.5 * cy * cy * (north - 2.0 * c + south))
+    out = (-0.5 * cx * (east - west) + 0.5 * cx * cx * (east - 2.0 * c + west)
+           - 0.5 * cy * (north - south) + 0.5 * cy * cy * (north - 2.0 * c + south))
+    if p.lw_cross:
+        ne, nw = g[:, 2:, 2:], g[:, 2:, :-2]
+        se, sw = g[:, :-2, 2:], g[:, :-2, :-2]
+        out = out + 0.25 * cx * cy * (ne - nw - se + sw)
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -342,8 +360,18 @@ def lax_wendroff(g, p: Params):
 # ---------------------------------------------------------------------------
 
 def step(f, p: Params):
-    """One time step: f^{n+1} = f^n - dt C(f^n) + LW(f^n) (forward Euler)."""
+    """One time step: f^{n+1} = f^n - dt C(f^n) + LW(f^n) (forward Euler).
+
+    With p.split the populations collide first and the post-collision
+    populations h = f - dt C(f) are convected: f^{n+1} = h + LW(h).  The
+    collision acts on the ghost cells too, which leaves them what the
+    boundary rules give for h (an equilibrium ghost does not change under
+    collision, and a copied ghost collides like its source cell).
+    """
     g = fill_ghosts(f, p)
+    if p.split:
+        h = g - p.dt * collision(g, p)
+        return h[:, 1:-1, 1:-1] + lax_wendroff(h, p)
     return f - p.dt * collision(f, p) + lax_wendroff(g, p)
 
 
@@ -379,7 +407,7 @@ def evolve_window(rho, ux, uy, T, p: Params, x0: int, x1: int, y0: int, y1: int,
     wbc = [bc[XLO] if x0 == 0 else BC_NONE, bc[XHI] if x1 == nx else BC_NONE,
            bc[YLO] if y0 == 0 else BC_NONE, bc[YHI] if y1 == ny else BC_NONE]
     wp = Params(gamma=p.gamma, s=p.s, dt=p.dt, dx=p.dx, dy=p.dy, eta0=p.eta0,
-                bc=wbc, side_state=p.side_state)
+                bc=wbc, side_state=p.side_state, split=p.split, lw_cross=p.lw_cross)
     sl = (slice(y0, y1), slice(x0, x1))
     f = init_populations(np.asarray(rho)[sl], np.asarray(ux)[sl],
                          np.asarray(uy)[sl], np.asarray(T)[sl], wp)
