@@ -32,15 +32,15 @@ HEADLINE_TILE_ROWS = 6              # what the tile autotuner picks for this gri
 # the 6 step dispatches) of
 #   bench.py --steps 5 --warmup 1 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,314.9 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,315.3 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this tile height; otherwise the roofline
 # reports traffic = null.
 MEASURED_TRAFFIC = {
-    "digest": "49021005b3ee4fda8bbb1f295169ca55a8c9d463decabe74a0360c1b6cdcfb29",
+    "digest": "7add45a4cb19a1e8a0a9817a71186c76318f4641a016350af520d22c25c81ddf",
     "tile_rows": HEADLINE_TILE_ROWS,
-    "fetch_kib": 709010.5, "fetch_copy_kib": 524314.9,
-    "write_kib": 1048576.1, "write_copy_kib": 1048576.0,
+    "fetch_kib": 709772.4, "fetch_copy_kib": 524315.3,
+    "write_kib": 1048576.5, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
@@ -94,11 +94,13 @@ def _events_time(stream, fn, nsteps):
     return e0.elapsed_time(e1) / 1e3
 
 
-def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0):
+def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, scheme=None):
     import torch
 
     from paper_1004_5442_amd.solver import solver_for_case
     s = solver_for_case(case, precision)
+    if scheme:
+        s.set_scheme(**scheme)
     if tile_rows:
         s.set_tile(tile_rows)
     elif autotune:
@@ -308,6 +310,13 @@ def main():
                 "mlups": round(rr["mlups"], 1),
                 "effective_GBs": roofline(rp, pr, rr)["achieved"],
                 "note": "fits the 256 MB Infinity Cache: effective, not HBM, bandwidth"}
+        variants = {}
+        for name, sch, bps in (("split", {"split": True}, 256), ("lw_cross", {"lw_cross": True}, 128),
+                               ("split_lw_cross", {"split": True, "lw_cross": True}, 256)):
+            rv = time_solver(head, prec, k, 3, autotune=False, scheme=sch)
+            variants[name] = {"mlups": round(rv["mlups"], 1), "bytes_per_site": bps,
+                              "roofline_frac": round(bps * rv["mlups"] * 1e6 / 1e9 / HBM_PEAK_GBS, 4)}
+        extra["scheme_variants_4096_fp32_eq64"] = variants
         rm = W.rm_instability()
         for pr in ("fp32_eq64", "fp64"):
             rr = time_solver(rm, pr, 4 * k, 64)

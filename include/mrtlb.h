@@ -156,6 +156,25 @@ int mrt_sync(mrt_ctx* ctx);
 int mrt_set_tile(mrt_ctx* ctx, int rows_per_item, int grid_blocks);
 int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
 
+/* Scheme variants (the paper's discretisation passage admits three
+ * readings; section "Construction", last paragraph before Fig. 1):
+ *   0                      unsplit forward Euler, per-axis Lax-Wendroff
+ *                          (five points): f + LW(f) - dt C(f)   [default]
+ *   MRT_SCHEME_SPLIT       collide, then convect the post-collision state:
+ *                          h = f - dt C(f), f^{n+1} = h + LW(h)
+ *   MRT_SCHEME_LW_CROSS    full 2D Lax-Wendroff: adds the mixed-derivative
+ *                          term (c_x c_y / 4)(f_NE - f_NW - f_SE + f_SW)
+ * (flags combine).  Corner ghosts, which only the nine-point stencil reads,
+ * follow the y side's rule applied to the x-side ghost next to them.  The
+ * variants run one thread per cell (the split form in two passes through a
+ * library-owned third state buffer, allocated here on first use); they are
+ * for comparing readings, the default is the tuned path.  mrt_step_buffers,
+ * the checkpointed calls and the adjoint support the default only
+ * (MRT_EINVAL otherwise).  Errors: MRT_EINVAL (unknown flags), MRT_ENOMEM. */
+#define MRT_SCHEME_SPLIT 1
+#define MRT_SCHEME_LW_CROSS 2
+int mrt_set_scheme(mrt_ctx* ctx, int flags);
+
 /* Time candidate tile shapes on the current state (the populations are saved
  * and restored) and keep the fastest.  Synchronises. */
 int mrt_autotune(mrt_ctx* ctx, int steps_per_trial);

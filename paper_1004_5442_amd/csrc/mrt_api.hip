@@ -23,6 +23,8 @@ hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, i
                    hipStream_t st);
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                   void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
+hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool reflect,
+                     const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
                      const void* fn, void* lout, double* partial, bool accumulate, double* ds,
                      hipStream_t st);
@@ -115,6 +117,12 @@ int fill_inst(Inst& I, int nx, int ny, const int bc[4], const mrt_params* p, std
             I.lwf[a][k][0] = float(I.lw[a][k][0]);
             I.lwf[a][k][1] = float(I.lw[a][k][1]);
         }
+    for (int k = 0; k < 4; ++k) {
+        // diagonal shells: |v_x| = |v_y| = shell_speed(k)
+        const double v = mrt::shell_speed(k);
+        I.lwc[k] = k < 2 ? 0.0 : 0.25 * (v * p->dt / p->dx) * (v * p->dt / p->dy);
+        I.lwcf[k] = float(I.lwc[k]);
+    }
     for (int side = 0; side < 4; ++side) {
         I.bc[side] = bc[side];
         for (int i = 0; i < 16; ++i) I.ghost[side][i] = 0.0;
@@ -253,6 +261,8 @@ struct mrt_ctx {
     bool nt = false;                 // non-temporal population stores (large grids)
     GraphCache graphs;               // captured steps of mrt_step
     bool eager = false;              // launch step by step (the tile autotuner)
+    int scheme = 0;                  // MRT_SCHEME_* flags
+    void* f_tmp = nullptr;           // post-collision state of the split scheme
     Item* d_items_adj = nullptr;     // work items of the adjoint kernel (finer bands)
     int nitems_adj = 0;
     double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
@@ -276,6 +286,8 @@ int fill_eq_ghosts(mrt_ctx* c) {
     if (!has_kind(c->bc, MRT_BC_EQ)) return MRT_OK;
     for (int k = 0; k < 2; ++k)
         HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), c->f[k], 2, c->stream));
+    if (c->f_tmp)
+        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), c->f_tmp, 2, c->stream));
     return MRT_OK;
 }
 
@@ -452,11 +464,16 @@ int mrt_step(mrt_ctx* c, int n) {
     const int perim = 2 * (c->nx + c->ny);
     const bool reflect = has_kind(c->bc, MRT_BC_REFLECT);
     // one step reading buffer `cur`: reflecting-wall ghosts, then the step
+    // (the split scheme needs no ghosts of f: it collides first and refills
+    // the ghosts of the post-collision state itself)
     auto enqueue = [&](int cur, hipStream_t st) -> hipError_t {
-        if (reflect) {
+        if (reflect && !(c->scheme & MRT_SCHEME_SPLIT)) {
             const hipError_t e = mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[cur], 1, st);
             if (e != hipSuccess) return e;
         }
+        if (c->scheme)
+            return mrt::k_variant(c->prec, c->d_inst, c->nx, c->ny, c->scheme, reflect, c->f[cur],
+                                  c->f[1 - cur], c->f_tmp, c->d_health, st);
         return mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[cur], c->f[1 - cur],
                            c->d_health, c->grid, c->nt, st);
     };
@@ -475,6 +492,7 @@ int mrt_step_buffers(mrt_ctx* c, const void* fin, void* fout) {
     if (!c) return MRT_EINVAL;
     std::string& ctx_err = c->err;
     if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    if (c->scheme) return ctx_fail(c, MRT_EINVAL, "explicit-buffer steps use the default scheme only");
     if (!fin || !fout || fin == fout) return ctx_fail(c, MRT_EINVAL, "need two distinct buffers");
     if (has_kind(c->bc, MRT_BC_EQ) || has_kind(c->bc, MRT_BC_REFLECT))
         HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(fin), 3,
@@ -563,6 +581,26 @@ int mrt_set_tile(mrt_ctx* c, int rows, int grid) {
     return MRT_OK;
 }
 
+int mrt_set_scheme(mrt_ctx* c, int flags) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (flags < 0 || flags > (MRT_SCHEME_SPLIT | MRT_SCHEME_LW_CROSS))
+        return ctx_fail(c, MRT_EINVAL, "unknown scheme flags");
+    if ((flags & MRT_SCHEME_SPLIT) && !c->f_tmp) {
+        const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));
+        if (hipMalloc(&c->f_tmp, bytes) != hipSuccess) return ctx_fail(c, MRT_ENOMEM, "no memory for the split state");
+        HIPTRY(hipMemsetAsync(c->f_tmp, 0, bytes, c->stream));
+        if (c->params_set) {
+            const int rc = fill_eq_ghosts(c);
+            if (rc != MRT_OK) return rc;
+        }
+        HIPTRY(hipStreamSynchronize(c->stream));
+    }
+    c->scheme = flags;
+    c->graphs.clear();
+    return MRT_OK;
+}
+
 int mrt_get_tile(const mrt_ctx* c, int* rows, int* grid) {
     if (!c) return MRT_EINVAL;
     if (rows) *rows = c->rows;
@@ -635,6 +673,7 @@ void mrt_destroy(mrt_ctx* c) {
     if (c->d_inst) (void)hipFree(c->d_inst);
     if (c->d_items) (void)hipFree(c->d_items);
     if (c->d_items_adj) (void)hipFree(c->d_items_adj);
+    if (c->f_tmp) (void)hipFree(c->f_tmp);
     c->graphs.clear();
     if (c->d_stage) (void)hipFree(c->d_stage);
     if (c->d_partial) (void)hipFree(c->d_partial);
@@ -657,6 +696,7 @@ int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* la
     std::string& ctx_err = c->err;
     if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
     if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
+    if (c->scheme) return ctx_fail(c, MRT_EINVAL, "the adjoint is of the default scheme only");
     if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
         return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
     HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, lam_next, f_n, lam_n,
@@ -695,6 +735,7 @@ int mrt_adjoint_sweep(mrt_ctx* c, const void* const* checkpoints, int segment, i
     std::string& ctx_err = c->err;
     if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
     if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
+    if (c->scheme) return ctx_fail(c, MRT_EINVAL, "the adjoint is of the default scheme only");
     if (!lam || !lam_tmp || lam == lam_tmp || !ds || segment < 1 || nsteps < 0 ||
         (nsteps > 0 && !checkpoints) || (segment > 1 && nsteps > 1 && !work))
         return ctx_fail(c, MRT_EINVAL, "bad adjoint-sweep arguments");

@@ -40,6 +40,10 @@ struct Inst {
     // (for a component -c the two swap); they sum to c^2.
     double lw[2][4][2];
     float lwf[2][4][2];
+    // mixed-derivative weight of the nine-point stencil per shell:
+    // |c_x c_y| / 4 (zero on the axis shells)
+    double lwc[4];
+    float lwcf[4];
     double ghost[4][16];   // f^eq of each MRT_BC_EQ side
 };
 

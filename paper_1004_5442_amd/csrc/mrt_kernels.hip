@@ -118,10 +118,12 @@ struct Weights;
 template <>
 struct Weights<float> {
     __device__ static float get(const Inst* P, int ax, int k, int j) { return P->lwf[ax][k][j]; }
+    __device__ static float cross(const Inst* P, int k) { return P->lwcf[k]; }
 };
 template <>
 struct Weights<double> {
     __device__ static double get(const Inst* P, int ax, int k, int j) { return P->lw[ax][k][j]; }
+    __device__ static double cross(const Inst* P, int k) { return P->lwc[k]; }
 };
 
 // ------------------------------------------------------------------ ghosts
@@ -131,14 +133,80 @@ struct Weights<double> {
 // the reflected equilibria of MRT_BC_REFLECT sides (rewritten before every
 // step from the adjacent cell with its normal velocity reversed, `mode`
 // bit 0).  Ghosts x = -1 / x = nx for 0 <= y < ny, y = -1 / y = ny for
-// 0 <= x < nx; corners are never read.
+// 0 <= x < nx, and the four corners, which only the nine-point stencil
+// reads: a corner is the y side's rule applied to the x-side ghost next to
+// it (x sides first, then y sides over the full width), written where both
+// its sides keep ghosts in the ring (EQ or REFLECT); otherwise the index
+// remap reaches it through an interior row or column.
+// The reflecting-wall ghost of a cell: f^eq of its moments with the
+// velocity component along `axis` (0: x, 1: y) reversed (section (d)).
+template <typename C, typename S>
+__device__ __forceinline__ void reflected_eq(const S in[16], int axis, C b, C binv, S out[16]) {
+    C f[16], m[16], eq[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = C(in[i]);
+    pops_to_moments(f, m);
+    equilibrium_moments(m[0], axis == 0 ? -m[1] : m[1], axis == 0 ? m[2] : -m[2], m[3], b, binv, eq);
+    moments_to_pops(eq, o);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) out[i] = S(o[i]);
+}
+
+// Corner c (0: (-1, -1), 1: (nx, -1), 2: (-1, ny), 3: (nx, ny)) of the
+// ghost ring (see ghost_kernel).
+template <typename S, typename C>
+__device__ void ghost_corner(const Inst* __restrict__ P, S* __restrict__ f, int c, int mode) {
+    const int nx = P->nx, ny = P->ny;
+    const int xside = (c & 1) ? XHI : XLO, yside = c < 2 ? YLO : YHI;
+    const int xkind = P->bc[xside], ykind = P->bc[yside];
+    if (!(xkind == BC_EQ || xkind == BC_REFLECT)) return;
+    const bool do_eq = ykind == BC_EQ && (mode & 2);
+    const bool do_ref = ykind == BC_REFLECT && (mode & 1);
+    if (!do_eq && !do_ref) return;
+    const int gx = (c & 1) ? nx : -1, gy = c < 2 ? -1 : ny;
+    const int ix = (c & 1) ? nx - 1 : 0, iy = c < 2 ? 0 : ny - 1;
+    S* __restrict__ base = f + P->off + P->origin;
+    const long long plane = P->plane;
+    S g[16];
+    if (do_eq) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[yside][i]);
+    } else {
+        // the x-side ghost next to the corner, then its y reflection
+        C xg[16], m[16], eq[16], out[16];
+        if (xkind == BC_EQ) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) xg[i] = C(P->ghost[xside][i]);
+        } else {
+            const long long so = (long long)iy * P->pitch + ix;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) xg[i] = C(base[i * plane + so]);
+            pops_to_moments(xg, m);
+            equilibrium_moments(m[0], -m[1], m[2], m[3], C(P->b), C(P->binv), eq);
+            moments_to_pops(eq, xg);
+        }
+        pops_to_moments(xg, m);
+        equilibrium_moments(m[0], m[1], -m[2], m[3], C(P->b), C(P->binv), eq);
+        moments_to_pops(eq, out);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g[i] = S(out[i]);
+    }
+    const long long go = (long long)gy * P->pitch + gx;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) base[i * plane + go] = g[i];
+}
+
 template <typename S, typename C>
 __global__ __launch_bounds__(256) void ghost_kernel(const Inst* __restrict__ insts,
                                                     S* __restrict__ f, int mode) {
     const Inst* __restrict__ P = insts + blockIdx.y;
     const int nx = P->nx, ny = P->ny;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2 * (nx + ny)) return;
+    if (t >= 2 * (nx + ny) + 4) return;
+    if (t >= 2 * (nx + ny)) {
+        ghost_corner<S, C>(P, f, t - 2 * (nx + ny), mode);
+        return;
+    }
     int side, gx, gy, ix, iy;
     if (t < ny) {
         side = XLO; gx = -1; gy = t; ix = 0; iy = t;
@@ -162,16 +230,10 @@ __global__ __launch_bounds__(256) void ghost_kernel(const Inst* __restrict__ ins
         for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[side][i]);
     } else {
         const long long so = (long long)iy * P->pitch + ix;
-        C fc[16], m[16], eq[16], out[16];
+        S fc[16];
 #pragma unroll
-        for (int i = 0; i < 16; ++i) fc[i] = C(base[i * plane + so]);
-        pops_to_moments(fc, m);
-        const bool nxs = side == XLO || side == XHI;
-        equilibrium_moments(m[0], nxs ? -m[1] : m[1], nxs ? m[2] : -m[2], m[3], C(P->b),
-                            C(P->binv), eq);
-        moments_to_pops(eq, out);
-#pragma unroll
-        for (int i = 0; i < 16; ++i) g[i] = S(out[i]);
+        for (int i = 0; i < 16; ++i) fc[i] = base[i * plane + so];
+        reflected_eq<C>(fc, (side == XLO || side == XHI) ? 0 : 1, C(P->b), C(P->binv), g);
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) base[i * plane + go] = g[i];
@@ -499,6 +561,104 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_partials(const double* 
     }
 }
 
+// ------------------------------------------------- scheme variants
+//
+// The two other readings of the paper's time/space discretisation, one
+// thread per cell (they are for comparing readings, not the tuned path):
+//  * collide-then-stream: collide_kernel writes h = f - dt C(f), then
+//    cell_step_kernel<COLLIDE = false> convects h: f^{n+1} = h + LW(h);
+//  * nine-point Lax-Wendroff: cell_step_kernel<CROSS = true> adds the
+//    mixed-derivative term (|c_x c_y| / 4) s_x s_y (NE - NW - SE + SW) for the
+//    diagonal populations; with COLLIDE it is the unsplit step.
+// Neighbours come through the boundary remap of Inst (corner ghosts: see
+// ghost_kernel).
+
+__device__ __forceinline__ unsigned col_remap(const Inst* __restrict__ P, int x) {
+    return unsigned(x < 0 ? P->col_lo : (x >= P->nx ? P->col_hi : x));
+}
+
+template <typename S, typename C, bool COMP>
+__global__ __launch_bounds__(256) void collide_kernel(const Inst* __restrict__ P,
+                                                      const S* __restrict__ fin,
+                                                      S* __restrict__ fout,
+                                                      unsigned* __restrict__ health) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= P->nx) return;
+    const long long plane = P->plane;
+    const S* __restrict__ fi = fin + P->off;
+    S* __restrict__ fo = fout + P->off;
+    const C b = C(P->b), binv = C(P->binv);
+    for (int y = blockIdx.y; y < P->ny; y += gridDim.y) {
+        const unsigned o = row_offset(P, y) + unsigned(x);
+        S f[16], cdt[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) f[i] = (fi + (long long)i * plane)[o];
+        C rho, Pp;
+        cell_collision<C, COMP>(f, b, binv, P->sdt, cdt, rho, Pp);
+        if (!(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[o] = f[i] - cdt[i];
+    }
+}
+
+template <typename S, typename C, bool COMP, bool COLLIDE, bool CROSS>
+__global__ __launch_bounds__(256) void cell_step_kernel(const Inst* __restrict__ P,
+                                                        const S* __restrict__ fin,
+                                                        S* __restrict__ fout,
+                                                        unsigned* __restrict__ health) {
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= P->nx) return;
+    const long long plane = P->plane;
+    const S* __restrict__ fi = fin + P->off;
+    S* __restrict__ fo = fout + P->off;
+    const C b = C(P->b), binv = C(P->binv);
+    const unsigned xc = unsigned(x), xw = col_remap(P, x - 1), xe = col_remap(P, x + 1);
+    for (int y = blockIdx.y; y < P->ny; y += gridDim.y) {
+        const unsigned o = row_offset(P, y), on = row_offset(P, y + 1), os = row_offset(P, y - 1);
+        auto ld = [&](int i, unsigned row, unsigned col) -> S {
+            return (fi + (long long)i * plane)[row + col];
+        };
+        S f[16], cdt[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            f[i] = ld(i, o, xc);
+            cdt[i] = S(0);
+        }
+        if constexpr (COLLIDE) {
+            C rho, Pp;
+            cell_collision<C, COMP>(f, b, binv, P->sdt, cdt, rho, Pp);
+            if (!(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
+            S d = S(0);
+            if (sx != 0) {
+                const S E = ld(i, o, xe), W = ld(i, o, xw);
+                const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
+                const S we = sx > 0 ? wd : wu, ww = sx > 0 ? wu : wd;
+                d = we * E + (ww * W - (wd + wu) * f[i]);
+            }
+            if (sy != 0) {
+                const S N = ld(i, on, xc), So = ld(i, os, xc);
+                const S wd = Weights<S>::get(P, 1, k, 0), wu = Weights<S>::get(P, 1, k, 1);
+                const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
+                d += wn * N + (ws * So - (wd + wu) * f[i]);
+            }
+            if constexpr (CROSS) {
+                if (sx != 0 && sy != 0) {
+                    const S ne = ld(i, on, xe), nw = ld(i, on, xw);
+                    const S se = ld(i, os, xe), sw = ld(i, os, xw);
+                    const S wc = Weights<S>::cross(P, k);
+                    const S sxy = S(sx * sy);
+                    d += sxy * wc * ((ne - nw) - (se - sw));
+                }
+            }
+            (fo + (long long)i * plane)[o + xc] = f[i] + (d - cdt[i]);
+        }
+    }
+}
+
 // ------------------------------------------------------- per-cell kernels
 
 __device__ __forceinline__ long long cell_offset(const Inst* __restrict__ P, long long c) {
@@ -657,7 +817,7 @@ static int grid_for(long long n) {
 // sides, bit 1: fixed-equilibrium sides.
 hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, int mode,
                    hipStream_t st) {
-    const dim3 grid((perim + 255) / 256, count);
+    const dim3 grid((perim + 4 + 255) / 256, count);   // + the four corners
     switch (prec) {
         case 0: hipLaunchKernelGGL((ghost_kernel<double, double>), grid, dim3(256), 0, st, insts, static_cast<double*>(f), mode); break;
         case 1: hipLaunchKernelGGL((ghost_kernel<float, float>), grid, dim3(256), 0, st, insts, static_cast<float*>(f), mode); break;
@@ -672,6 +832,47 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
         case 0: return launch_step<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
         case 1: return launch_step<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, st);
         default: return launch_step<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
+    }
+}
+
+// Variant step (scheme flags as in mrtlb.h: bit 0 collide-then-stream, bit 1
+// nine-point Lax-Wendroff) from fin to fout; `tmp` holds the post-collision
+// populations of the split form, whose reflecting ghosts are refilled
+// between the two passes.
+template <typename S, typename C, bool COMP>
+hipError_t launch_variant(const Inst* P, int nx, int ny, int scheme, bool reflect, const void* fin,
+                          void* fout, void* tmp, unsigned* health, hipStream_t st) {
+    const dim3 grid((nx + 255) / 256, ny < 65535 ? ny : 65535);
+    const S* in = static_cast<const S*>(fin);
+    S* out = static_cast<S*>(fout);
+    const bool split = scheme & 1, cross = scheme & 2;
+    if (split) {
+        S* h = static_cast<S*>(tmp);
+        hipLaunchKernelGGL((collide_kernel<S, C, COMP>), grid, dim3(256), 0, st, P, in, h, health);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        if (reflect) {
+            hipLaunchKernelGGL((ghost_kernel<S, C>), dim3((2 * (nx + ny) + 4 + 255) / 256, 1), dim3(256), 0, st,
+                               P, h, 1);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (cross)
+            hipLaunchKernelGGL((cell_step_kernel<S, C, COMP, false, true>), grid, dim3(256), 0, st, P, h, out, health);
+        else
+            hipLaunchKernelGGL((cell_step_kernel<S, C, COMP, false, false>), grid, dim3(256), 0, st, P, h, out, health);
+    } else {
+        hipLaunchKernelGGL((cell_step_kernel<S, C, COMP, true, true>), grid, dim3(256), 0, st, P, in, out, health);
+    }
+    return hipGetLastError();
+}
+
+hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool reflect,
+                     const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st) {
+    switch (prec) {
+        case 0: return launch_variant<double, double, false>(P, nx, ny, scheme, reflect, fin, fout, tmp, health, st);
+        case 1: return launch_variant<float, float, true>(P, nx, ny, scheme, reflect, fin, fout, tmp, health, st);
+        default: return launch_variant<float, double, false>(P, nx, ny, scheme, reflect, fin, fout, tmp, health, st);
     }
 }
 

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libmrtlb.so")
 MRT_OK, MRT_EINVAL, MRT_EDEVICE, MRT_ESTATE, MRT_EUNSTABLE, MRT_ENOMEM = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_eq64": 2}
 BC = {"periodic": 0, "eq": 1, "outflow": 2, "reflect": 3}
+SCHEME_SPLIT, SCHEME_LW_CROSS = 1, 2
 STATUS = {0: "MRT_OK", -1: "MRT_EINVAL", -2: "MRT_EDEVICE", -3: "MRT_ESTATE",
           -4: "MRT_EUNSTABLE", -5: "MRT_ENOMEM"}
 
@@ -62,6 +63,7 @@ _proto = {
     "mrt_sync": (c_int, [c_void_p]),
     "mrt_set_tile": (c_int, [c_void_p, c_int, c_int]),
     "mrt_get_tile": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int)]),
+    "mrt_set_scheme": (c_int, [c_void_p, c_int]),
     "mrt_autotune": (c_int, [c_void_p, c_int]),
     "mrt_destroy": (None, [c_void_p]),
     "mrt_last_error": (ctypes.c_char_p, [c_void_p]),

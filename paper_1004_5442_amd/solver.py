@@ -137,6 +137,11 @@ class Solver:
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(16, self.ny, self.nx)
         self._check(L.raw().mrt_set_populations(self._h, _host_ptr(f), 0))
 
+    def set_scheme(self, split: bool = False, lw_cross: bool = False):
+        """Select a reading of the discretisation (mrt_set_scheme)."""
+        flags = (L.SCHEME_SPLIT if split else 0) | (L.SCHEME_LW_CROSS if lw_cross else 0)
+        self._check(L.raw().mrt_set_scheme(self._h, flags))
+
     def set_tile(self, rows: int, grid: int = 0):
         self._check(L.raw().mrt_set_tile(self._h, int(rows), int(grid)))
 

@@ -7,13 +7,14 @@ BCMAP = {"periodic": mrt.BC_PERIODIC, "eq": mrt.BC_EQ, "outflow": mrt.BC_OUTFLOW
          "reflect": mrt.BC_REFLECT}
 
 
-def oracle_params(case):
+def oracle_params(case, split=False, lw_cross=False):
     return mrt.Params(gamma=case.gamma, s=case.s, dt=case.dt, dx=case.dx, dy=case.dy,
-                      eta0=case.eta0, bc=[BCMAP[b] for b in case.bc], side_state=case.side_state)
+                      eta0=case.eta0, bc=[BCMAP[b] for b in case.bc], side_state=case.side_state,
+                      split=split, lw_cross=lw_cross)
 
 
-def oracle_run(case, nsteps):
-    p = oracle_params(case)
+def oracle_run(case, nsteps, split=False, lw_cross=False):
+    p = oracle_params(case, split, lw_cross)
     f = mrt.init_populations(case.rho, case.ux, case.uy, case.T, p)
     return mrt.run(f, p, nsteps), p
 
