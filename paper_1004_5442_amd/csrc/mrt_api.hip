@@ -22,7 +22,7 @@ namespace mrt {
 hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, int mode,
                    hipStream_t st);
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
+                  void* fout, unsigned* health, int grid, bool nt, bool walls, hipStream_t st);
 hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool reflect,
                      const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
@@ -259,6 +259,7 @@ struct mrt_ctx {
     Item* d_items = nullptr;
     int nitems = 0, rows = 0, grid = 0;
     bool nt = false;                 // non-temporal population stores (large grids)
+    bool walls = false;              // the step kernel writes the reflecting-wall ghosts
     GraphCache graphs;               // captured steps of mrt_step
     bool eager = false;              // launch step by step (the tile autotuner)
     int scheme = 0;                  // MRT_SCHEME_* flags
@@ -279,15 +280,19 @@ int ctx_fail(mrt_ctx* c, int code, const std::string& msg) {
     return code;
 }
 
-// Equilibrium ghosts of MRT_BC_EQ sides into both population buffers (they
-// are never overwritten by a step).
-int fill_eq_ghosts(mrt_ctx* c) {
+// Ghost ring after the state was set from outside a step: the equilibrium
+// ghosts of MRT_BC_EQ sides into every population buffer (no step overwrites
+// them) and the reflecting-wall ghosts of the current state (from then on
+// each step kernel writes those of its own output).
+int fill_ghosts(mrt_ctx* c) {
     std::string& ctx_err = c->err;
-    if (!has_kind(c->bc, MRT_BC_EQ)) return MRT_OK;
-    for (int k = 0; k < 2; ++k)
-        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), c->f[k], 2, c->stream));
-    if (c->f_tmp)
-        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), c->f_tmp, 2, c->stream));
+    const int perim = 2 * (c->nx + c->ny);
+    if (has_kind(c->bc, MRT_BC_EQ)) {
+        for (int k = 0; k < 2; ++k) HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[k], 2, c->stream));
+        if (c->f_tmp) HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f_tmp, 2, c->stream));
+    }
+    if (has_kind(c->bc, MRT_BC_REFLECT))
+        HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[c->cur], 1, c->stream));
     return MRT_OK;
 }
 
@@ -326,6 +331,12 @@ int build_adjoint_items(mrt_ctx* c) {
 // larger than the 256 MB last-level cache: nothing of the new state can stay
 // cached until the next step anyway.  Smaller grids keep it cached.
 constexpr long long kNonTemporalBytes = 256LL << 20;
+
+// Grids with reflecting walls up to this many cells have the step kernel
+// write the wall ghosts of its output (one launch per step instead of two:
+// the launch latency dominates there); larger ones refill them with the
+// ghost kernel, which costs them less than the extra registers would.
+constexpr long long kWallsInKernelCells = 1LL << 22;
 
 int check_health(mrt_ctx* c) {
     std::string& ctx_err = c->err;
@@ -399,6 +410,7 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     if (build_items(c, default_rows(nx, ny)) != MRT_OK) return fail(MRT_EDEVICE);
     if (build_adjoint_items(c) != MRT_OK) return fail(MRT_EDEVICE);
     c->nt = (long long)bytes > kNonTemporalBytes;
+    c->walls = has_kind(bc, MRT_BC_REFLECT) && (long long)nx * ny <= kWallsInKernelCells;
     (void)ctx_err;
     *out = c;
     return MRT_OK;
@@ -422,7 +434,7 @@ int mrt_set_params(mrt_ctx* c, const mrt_params* p) {
     HIPTRY(hipMemcpyAsync(c->d_inst, &c->inst, sizeof(Inst), hipMemcpyHostToDevice, c->stream));
     c->params_set = true;
     if (c->fields_set) {
-        const int r = fill_eq_ghosts(c);
+        const int r = fill_ghosts(c);
         if (r != MRT_OK) return r;
     }
     HIPTRY(hipStreamSynchronize(c->stream));
@@ -450,7 +462,7 @@ int mrt_set_fields(mrt_ctx* c, const double* rho, const double* ux, const double
         HIPTRY(mrt::k_init(c->prec, c->d_inst, n, s, s + n, s + 2 * n, s + 3 * n, c->f[c->cur], c->stream));
     }
     c->fields_set = true;
-    const int r = fill_eq_ghosts(c);
+    const int r = fill_ghosts(c);
     if (r != MRT_OK) return r;
     if (!on_device) HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
@@ -463,11 +475,14 @@ int mrt_step(mrt_ctx* c, int n) {
     if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
     const int perim = 2 * (c->nx + c->ny);
     const bool reflect = has_kind(c->bc, MRT_BC_REFLECT);
-    // one step reading buffer `cur`: reflecting-wall ghosts, then the step
-    // (the split scheme needs no ghosts of f: it collides first and refills
-    // the ghosts of the post-collision state itself)
+    // one step reading buffer `cur`: reflecting-wall ghosts unless the step
+    // kernel wrote them with the previous step's output (c->walls), then the
+    // step.  The per-cell nine-point kernel writes none, so its ghosts
+    // (corners too) are always refilled (the split scheme refills those of
+    // its post-collision state itself)
+    const bool ghost_pass = reflect && (c->scheme == MRT_SCHEME_LW_CROSS || (c->scheme == 0 && !c->walls));
     auto enqueue = [&](int cur, hipStream_t st) -> hipError_t {
-        if (reflect && !(c->scheme & MRT_SCHEME_SPLIT)) {
+        if (ghost_pass) {
             const hipError_t e = mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[cur], 1, st);
             if (e != hipSuccess) return e;
         }
@@ -475,7 +490,7 @@ int mrt_step(mrt_ctx* c, int n) {
             return mrt::k_variant(c->prec, c->d_inst, c->nx, c->ny, c->scheme, reflect, c->f[cur],
                                   c->f[1 - cur], c->f_tmp, c->d_health, st);
         return mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[cur], c->f[1 - cur],
-                           c->d_health, c->grid, c->nt, st);
+                           c->d_health, c->grid, c->nt, c->walls, st);
     };
     if (n == 1 || c->eager) {
         for (int k = 0; k < n; ++k) {
@@ -498,7 +513,7 @@ int mrt_step_buffers(mrt_ctx* c, const void* fin, void* fout) {
         HIPTRY(mrt::k_ghost(c->prec, c->d_inst, 1, 2 * (c->nx + c->ny), const_cast<void*>(fin), 3,
                             c->stream));
     HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, fin, fout, c->d_health, c->grid,
-                       c->nt, c->stream));
+                       c->nt, c->walls, c->stream));
     return MRT_OK;
 }
 
@@ -554,7 +569,7 @@ int mrt_set_populations(mrt_ctx* c, const double* f, int on_device) {
         HIPTRY(hipFreeAsync(tmp, c->stream));
     }
     c->fields_set = true;
-    const int r = fill_eq_ghosts(c);
+    const int r = fill_ghosts(c);
     if (r != MRT_OK) return r;
     if (!on_device) HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
@@ -590,14 +605,16 @@ int mrt_set_scheme(mrt_ctx* c, int flags) {
         const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));
         if (hipMalloc(&c->f_tmp, bytes) != hipSuccess) return ctx_fail(c, MRT_ENOMEM, "no memory for the split state");
         HIPTRY(hipMemsetAsync(c->f_tmp, 0, bytes, c->stream));
-        if (c->params_set) {
-            const int rc = fill_eq_ghosts(c);
-            if (rc != MRT_OK) return rc;
-        }
-        HIPTRY(hipStreamSynchronize(c->stream));
     }
     c->scheme = flags;
     c->graphs.clear();
+    // the variants do not write the reflecting ghosts of their output: make
+    // the ring current for whichever scheme runs next
+    if (c->params_set && c->fields_set) {
+        const int rc = fill_ghosts(c);
+        if (rc != MRT_OK) return rc;
+    }
+    HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
 }
 
@@ -830,6 +847,7 @@ struct mrt_batch {
     Item* d_items = nullptr;
     int nitems = 0, rows = 0, grid = 0;
     bool nt = false;                        // non-temporal population stores
+    bool walls = false;                     // the step kernel writes the reflecting-wall ghosts
     double* d_stage = nullptr;
     unsigned* d_health = nullptr;
     GraphCache graphs;                      // captured steps
@@ -903,6 +921,7 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
     b->total_elems = off;
     const size_t bytes = size_t(off) * elem_size(precision);
     b->nt = (long long)bytes > kNonTemporalBytes;
+    b->walls = b->any_reflect && b->total_cells <= kWallsInKernelCells;
     auto fail = [&](int code) {
         mrt_batch_destroy(b);
         return code;
@@ -940,10 +959,12 @@ int mrt_batch_set_fields(mrt_batch* b, int i, const double* rho, const double* u
     HIPTRY(hipMemcpyAsync(s + 2 * n, uy, by, hipMemcpyHostToDevice, b->stream));
     HIPTRY(hipMemcpyAsync(s + 3 * n, T, by, hipMemcpyHostToDevice, b->stream));
     HIPTRY(mrt::k_init(b->prec, b->d_insts + i, n, s, s + n, s + 2 * n, s + 3 * n, b->f[b->cur], b->stream));
-    // equilibrium ghosts of this instance in both buffers
+    // equilibrium ghosts of this instance in both buffers, reflecting ones
+    // of its current state
     const int perim = 2 * (b->insts[i].nx + b->insts[i].ny);
     for (int k = 0; k < 2; ++k)
         HIPTRY(mrt::k_ghost(b->prec, b->d_insts + i, 1, perim, b->f[k], 2, b->stream));
+    HIPTRY(mrt::k_ghost(b->prec, b->d_insts + i, 1, perim, b->f[b->cur], 1, b->stream));
     HIPTRY(hipStreamSynchronize(b->stream));
     return MRT_OK;
 }
@@ -952,13 +973,15 @@ int mrt_batch_step(mrt_batch* b, int n) {
     if (!b || n < 0) return MRT_EINVAL;
     std::string& ctx_err = b->err;
     if (n == 0) return MRT_OK;
+    // reflecting-wall ghosts: written by the step kernel with its output
+    // (b->walls), else refilled before each step
     auto enqueue = [&](int cur, hipStream_t st) -> hipError_t {
-        if (b->any_reflect) {
+        if (b->any_reflect && !b->walls) {
             const hipError_t e = mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[cur], 1, st);
             if (e != hipSuccess) return e;
         }
         return mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[cur], b->f[1 - cur],
-                           b->d_health, b->grid, b->nt, st);
+                           b->d_health, b->grid, b->nt, b->walls, st);
     };
     HIPTRY(run_graphs(b->graphs, b->cur, n, b->stream, enqueue));
     return MRT_OK;

@@ -130,9 +130,10 @@ struct Weights<double> {
 
 // Ghost cells that are not read through the index remap of Inst: the
 // equilibria of MRT_BC_EQ sides (written once per buffer, `mode` bit 1) and
-// the reflected equilibria of MRT_BC_REFLECT sides (rewritten before every
-// step from the adjacent cell with its normal velocity reversed, `mode`
-// bit 0).  Ghosts x = -1 / x = nx for 0 <= y < ny, y = -1 / y = ny for
+// the reflected equilibria of MRT_BC_REFLECT sides (the adjacent cell with
+// its normal velocity reversed, `mode` bit 0: for a state set from outside a
+// step, and before each step of the per-cell variant kernels; the step
+// kernel writes those of its own output).  Ghosts x = -1 / x = nx for 0 <= y < ny, y = -1 / y = ny for
 // 0 <= x < nx, and the four corners, which only the nine-point stencil
 // reads: a corner is the y side's rule applied to the x-side ghost next to
 // it (x sides first, then y sides over the full width), written where both
@@ -272,7 +273,7 @@ struct EdgeBuf {
 // index of an x-moving population among the 12 (0, 2, 4, 6, 8..15)
 constexpr int xslot(int i) { return i < 8 ? i >> 1 : i - 4; }
 
-template <typename S, typename C, bool COMP, bool NT>
+template <typename S, typename C, bool COMP, bool NT, bool WALLS>
 __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, int y0, int y1,
                                            const S* __restrict__ fin, S* __restrict__ fout,
                                            unsigned* __restrict__ health, EdgeBuf<S>& lds) {
@@ -306,6 +307,13 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
     const int nwave = lane == 0 ? wv - 1 : wv + 1;
     const int nside = lane == 0 ? 1 : 0;
     const bool hlds = edge_lane && !hmem;
+    // reflecting walls (see the end of body)
+    const bool ref_ylo = P->bc[YLO] == BC_REFLECT, ref_yhi = P->bc[YHI] == BC_REFLECT;
+    const int wx0 = x0 + 64 * wv;
+    const bool ref_xwave = (P->bc[XLO] == BC_REFLECT && wx0 == 0) ||
+                           (P->bc[XHI] == BC_REFLECT && wx0 <= nx - 1 && nx - 1 < wx0 + 64);
+    const bool ref_w = P->bc[XLO] == BC_REFLECT && x == 0;
+    const bool ref_e = P->bc[XHI] == BC_REFLECT && x == nx - 1;
 
     auto publish = [&](const S (&r)[16], int slot) {
         if (edge_lane) {
@@ -371,6 +379,40 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
             else
                 *dst = v;
         }
+        // WALLS: reflecting walls of the next step.  The ghosts of the new
+        // state next to a wall are the reflections of the wall cells just
+        // stored, so the lanes that stored them read them back and write the
+        // ghosts (no ghost pass between steps: one launch per step instead
+        // of two, which pays on small, launch-bound grids; the extra
+        // registers cost large grids more than the ghost launch saves)
+        const bool wall_lo = ref_ylo && y == 0, wall_hi = ref_yhi && y == P->ny - 1;
+        if (WALLS && (wall_lo || wall_hi || ref_xwave)) {
+            S v[16], g[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = (fo + (long long)i * plane)[o + xs];
+            if (wall_lo || wall_hi) {
+                reflected_eq<C>(v, 1, b, binv, g);
+                if (wall_lo) {
+                    const unsigned og = row_offset(P, -1) + xs;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[og] = g[i];
+                }
+                if (wall_hi) {
+                    const unsigned og = row_offset(P, P->ny) + xs;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[og] = g[i];
+                }
+            }
+            if (ref_xwave) {
+                reflected_eq<C>(v, 0, b, binv, g);
+                if (ref_w || ref_e) {
+                    // column -1 or nx of this row (32-bit sum: o >= 64)
+                    const unsigned gx = ref_w ? o - 1u : o + unsigned(nx);
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[gx] = g[i];
+                }
+            }
+        }
         // hand row y+1's edge values to the neighbour waves
         if (more) publish(rp, (y + 1) & 1);
         __syncthreads();
@@ -401,8 +443,14 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
     }
 }
 
-template <typename S, typename C, bool COMP, bool NT>
-__global__ __launch_bounds__(256) void step_kernel(const Inst* __restrict__ insts,
+// Waves per SIMD the WALLS step kernel is held to: three for FP32 storage
+// with FP64 collision (168 VGPRs, as the plain kernel uses by itself), two
+// otherwise.  The plain kernel is left to the compiler.
+template <typename S, bool COMP, bool WALLS>
+constexpr int step_waves() { return (WALLS && sizeof(S) == 4 && !COMP) ? 3 : 1; }
+
+template <typename S, typename C, bool COMP, bool NT, bool WALLS>
+__global__ __launch_bounds__(256, (step_waves<S, COMP, WALLS>())) void step_kernel(const Inst* __restrict__ insts,
                                                    const Item* __restrict__ items, int nitems,
                                                    const S* __restrict__ fin, S* __restrict__ fout,
                                                    unsigned* __restrict__ health) {
@@ -417,7 +465,7 @@ __global__ __launch_bounds__(256) void step_kernel(const Inst* __restrict__ inst
         const int w = (q & 7) * per + (q >> 3);
         if (w >= nitems) continue;
         const Item it = items[w];
-        step_block<S, C, COMP, NT>(insts + it.inst, it.x0, it.y0, it.y1, fin, fout, health, lds);
+        step_block<S, C, COMP, NT, WALLS>(insts + it.inst, it.x0, it.y0, it.y1, fin, fout, health, lds);
         __syncthreads();   // the next item reuses the edge buffer
     }
 }
@@ -787,17 +835,25 @@ __global__ __launch_bounds__(256) void import_kernel(const Inst* __restrict__ P,
 
 // -------------------------------------------------------- launch wrappers
 
+template <typename S, typename C, bool COMP, bool NT, bool WALLS>
+void launch_step_kernel(int blocks, const Inst* insts, const Item* items, int nitems,
+                        const void* fin, void* fout, unsigned* health, hipStream_t st) {
+    hipLaunchKernelGGL((step_kernel<S, C, COMP, NT, WALLS>), dim3(blocks), dim3(256), 0, st, insts,
+                       items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+}
+
 template <typename S, typename C, bool COMP>
 hipError_t launch_step(const Inst* insts, const Item* items, int nitems, const void* fin,
-                       void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+                       void* fout, unsigned* health, int grid, bool nt, bool walls, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     const int blocks = grid > 0 ? grid : 8 * ((nitems + 7) / 8);
-    if (nt)
-        hipLaunchKernelGGL((step_kernel<S, C, COMP, true>), dim3(blocks), dim3(256), 0, st, insts,
-                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
-    else
-        hipLaunchKernelGGL((step_kernel<S, C, COMP, false>), dim3(blocks), dim3(256), 0, st, insts,
-                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+    if (nt) {
+        if (walls) launch_step_kernel<S, C, COMP, true, true>(blocks, insts, items, nitems, fin, fout, health, st);
+        else launch_step_kernel<S, C, COMP, true, false>(blocks, insts, items, nitems, fin, fout, health, st);
+    } else {
+        if (walls) launch_step_kernel<S, C, COMP, false, true>(blocks, insts, items, nitems, fin, fout, health, st);
+        else launch_step_kernel<S, C, COMP, false, false>(blocks, insts, items, nitems, fin, fout, health, st);
+    }
     return hipGetLastError();
 }
 
@@ -826,12 +882,14 @@ hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, i
     return hipGetLastError();
 }
 
+// walls: the kernel writes the reflecting-wall ghosts of its output (see
+// step_block); otherwise the caller refills them before each step.
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+                  void* fout, unsigned* health, int grid, bool nt, bool walls, hipStream_t st) {
     switch (prec) {
-        case 0: return launch_step<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
-        case 1: return launch_step<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, st);
-        default: return launch_step<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        case 0: return launch_step<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, walls, st);
+        case 1: return launch_step<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, walls, st);
+        default: return launch_step<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, walls, st);
     }
 }
 
