@@ -96,13 +96,15 @@ typedef struct mrt_params {
  *            mrt_population_bytes(nx, ny, precision) bytes, which must outlive
  *            the context.
  * stream:    hipStream_t to run on (NULL = null stream).
- * Errors: MRT_EINVAL (nx, ny < 1, bad precision or bc), MRT_ENOMEM,
- * MRT_EDEVICE.  On error *out is NULL. */
+ * Errors: MRT_EINVAL (nx, ny < 1, a grid of 2^32 or more padded elements
+ * per state (FP32: beyond ~16000 x 16000 cells; the kernels use 32-bit
+ * offsets), bad precision or bc), MRT_ENOMEM, MRT_EDEVICE.  On error *out
+ * is NULL. */
 int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
                   void* const f_dev[2], void* stream);
 
 /* Bytes of one population buffer for a grid (ny + 2 rows of 16 padded
- * population sub-rows). */
+ * population sub-rows); 0 for a grid that mrt_init_grid rejects by size. */
 long long mrt_population_bytes(int nx, int ny, int precision);
 
 /* Row stride (pitch), population stride (plane) and offset of cell (0, 0)
@@ -263,7 +265,8 @@ typedef struct mrt_instance {
     mrt_params params;
 } mrt_instance;
 
-/* Errors: MRT_EINVAL (count < 1, any instance invalid), MRT_ENOMEM. */
+/* Errors: MRT_EINVAL (count < 1, any instance invalid or too large, as in
+ * mrt_init_grid), MRT_ENOMEM. */
 int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int precision,
                      void* stream);
 /* Fields of instance i (host doubles, ny*nx each).  Synchronises. */

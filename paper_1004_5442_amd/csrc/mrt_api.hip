@@ -67,6 +67,13 @@ long long plane_for(int nx) { return sub_for(nx); }
 long long origin_for(int nx) { return pitch_for(nx) + 64; }
 long long elems_for(int nx, int ny) { return (long long)(ny + 2) * pitch_for(nx) + 512; }
 
+// The kernels index an instance with 32-bit element offsets (their row
+// offsets and columns are unsigned 32-bit sums): an instance must stay below
+// 2^32 elements (FP32 storage: 16 GiB per state, e.g. 16000 x 16000 cells).
+bool size_ok(int nx, int ny) {
+    return nx >= 1 && ny >= 1 && elems_for(nx, ny) < (1LL << 32);
+}
+
 bool bc_ok(const int bc[4]) {
     for (int k = 0; k < 4; ++k)
         if (bc[k] < MRT_BC_PERIODIC || bc[k] > MRT_BC_REFLECT) return false;
@@ -357,7 +364,7 @@ int check_health(mrt_ctx* c) {
 extern "C" {
 
 long long mrt_population_bytes(int nx, int ny, int precision) {
-    if (nx < 1 || ny < 1) return 0;
+    if (!size_ok(nx, ny)) return 0;
     return elems_for(nx, ny) * (long long)elem_size(precision);
 }
 
@@ -365,7 +372,7 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
                   void* const f_dev[2], void* stream) {
     if (!out) return MRT_EINVAL;
     *out = nullptr;
-    if (nx < 1 || ny < 1 || precision < 0 || precision > 2 || !bc || !bc_ok(bc)) return MRT_EINVAL;
+    if (!size_ok(nx, ny) || precision < 0 || precision > 2 || !bc || !bc_ok(bc)) return MRT_EINVAL;
     mrt_ctx* c = new mrt_ctx();
     std::string& ctx_err = c->err;
     c->nx = nx;
@@ -893,7 +900,7 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
     int maxny = 1;
     for (int i = 0; i < count; ++i) {
         const mrt_instance& d = desc[i];
-        if (d.nx < 1 || d.ny < 1 || !bc_ok(d.bc)) {
+        if (!size_ok(d.nx, d.ny) || !bc_ok(d.bc)) {
             delete b;
             return MRT_EINVAL;
         }

@@ -241,9 +241,11 @@ __global__ __launch_bounds__(256) void ghost_kernel(const Inst* __restrict__ ins
 }
 
 // offset in a plane of row y, -1 <= y <= ny, with the boundary remap
+// (unsigned arithmetic: r = -1 wraps to origin - pitch; the library keeps
+// every instance below 2^32 elements, so the offset itself never wraps)
 __device__ __forceinline__ unsigned row_offset(const Inst* __restrict__ P, int y) {
     const int r = y < 0 ? P->row_lo : (y >= P->ny ? P->row_hi : y);
-    return unsigned(P->origin + r * P->pitch);
+    return unsigned(P->origin) + unsigned(r) * unsigned(P->pitch);
 }
 
 // ------------------------------------------------------------------- step
