@@ -32,15 +32,15 @@ HEADLINE_TILE_ROWS = 6              # what the tile autotuner picks for this gri
 # the 6 step dispatches) of
 #   bench.py --steps 5 --warmup 1 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,315.1 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,315.6 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this tile height; otherwise the roofline
 # reports traffic = null.
 MEASURED_TRAFFIC = {
-    "digest": "900fbd93c896788413b06584ce6858ef9b1f41a388c4fe23b99992f6023a95c7",
+    "digest": "6b49cf2b07f4e9f53d4cf91be71e3c772d304a302c7645e7710ea007116dd879",
     "tile_rows": HEADLINE_TILE_ROWS,
-    "fetch_kib": 709806.9, "fetch_copy_kib": 524315.1,
-    "write_kib": 1048576.3, "write_copy_kib": 1048576.0,
+    "fetch_kib": 709937.8, "fetch_copy_kib": 524315.6,
+    "write_kib": 1048576.1, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 

@@ -165,3 +165,22 @@ def test_shock_bubble_4096_mirror_symmetry(precision):
     assert all(err[k] < tol[k] for k in err), (err, tol)
     # and the run moved: the shock has advanced several cells
     assert float(rho[n // 2, int(0.1 * n) + 10]) > 1.5
+
+
+def test_largest_grids_use_the_full_32_bit_offset_range():
+    """12000 x 12000 cells, FP32 storage: 2.36e9 elements per state, past
+    the 2^31 that signed 32-bit row offsets would reach.  A few steps, then
+    patches at the shock, the bubble, the walls and the corners against the
+    oracle."""
+    n = 12000
+    case = W.shock_bubble(n=n)
+    print(f"case {case.name} fp32_eq64 {NSTEPS} steps", flush=True)
+    s = solver_for_case(case, "fp32_eq64")
+    assert s.population_bytes() > 4 * 2 ** 31
+    s.set_tile(HEADLINE_TILE_ROWS)
+    s.step(NSTEPS)
+    s.sync()
+    centres = [(int(0.1 * n), n // 2), (int(0.1 * n), 0), (int(0.15 * n), n // 2),
+               (n // 2, n - 1), (0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1)]
+    compare(case, s, centres, NSTEPS, "fp32_eq64")
+    s.close()
