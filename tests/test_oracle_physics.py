@@ -267,3 +267,30 @@ def test_linear_stability_interval():
     outside = mrt.Params(gamma=1.4, s=rates(3 / dt, 3 / dt, 3 / dt, 3 / dt), dt=dt, dx=0.01, dy=0.01)
     assert stability.max_amplification(st, inside, 17) <= 1 + 1e-12
     assert stability.max_amplification(st, outside, 17) > 1.5
+
+
+def test_small_perturbations_follow_the_amplification_matrix():
+    """The linear-stability tool is the scheme's own linearisation: a small
+    Fourier perturbation of a uniform moving equilibrium, advanced by the
+    nonlinear oracle step, equals G(theta)^N applied to it (G from
+    oracle/stability.py), to first order in the amplitude."""
+    n, N, eps = 16, 25, 1e-6
+    p = mrt.Params(gamma=1.4, s=rates(3e3, 6e3, 0.71, 8e3), dt=1e-4, dx=1.0 / n, dy=1.0 / n)
+    base = (1.0, 0.3, -0.2, 0.9)
+    f0 = mrt.feq(*base, p.b).reshape(16, 1, 1)
+    rng = np.random.default_rng(2)
+    v = rng.standard_normal(16)
+    kx, ky = 1, 2
+    tx, ty = 2 * np.pi * kx / n, 2 * np.pi * ky / n
+    Y, X = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    phase = tx * X + ty * Y
+    f = f0 + eps * v.reshape(16, 1, 1) * np.cos(phase)
+    for _ in range(N):
+        f = mrt.step(f, p)
+    # Fourier component at (kx, ky): the cosine's e^{+i phase} half
+    got = 2.0 * np.mean((f - f0) * np.exp(-1j * phase), axis=(1, 2)) / eps
+    G = stability.amplification_matrix(base, p, tx, ty)
+    want = np.linalg.matrix_power(G, N) @ v
+    assert np.allclose(got, want, rtol=0, atol=1e-5 * np.abs(want).max())
+    # and the transfer is not trivial: the mode changed over the run
+    assert np.abs(want - v).max() > 1e-2 * np.abs(v).max()
