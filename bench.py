@@ -106,6 +106,7 @@ def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, sche
     elif autotune:
         s.autotune(4)
     s.step(warmup)
+    s.prepare(steps)        # capture the step graphs outside the timed region
     s.sync()
     sec = _events_time(torch.cuda.current_stream(), s.step, steps)
     s.sync()      # raises if the run went unhealthy
@@ -126,6 +127,7 @@ def time_batch(steps, warmup):
     b = Batch(cases, "fp32_eq64")
     b.autotune(4)
     b.step(warmup)
+    b.prepare(steps)
     torch.cuda.synchronize()
     sec = _events_time(torch.cuda.current_stream(), b.step, steps)
     b.moments(0)              # raises if any instance went unhealthy

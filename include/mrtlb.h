@@ -130,6 +130,15 @@ int mrt_set_fields(mrt_ctx* ctx, const double* rho, const double* ux, const doub
  * the next synchronising call.  Errors: MRT_ESTATE, MRT_EINVAL (n < 0). */
 int mrt_step(mrt_ctx* ctx, int n);
 
+/* Capture (without running anything) the HIP graphs that a following
+ * mrt_step(ctx, n) will replay, so that their one-time capture and
+ * instantiation cost (about a millisecond for 64 steps) falls outside a timed
+ * region or a latency-critical loop.  Steps are replayed as n / 64 replays of
+ * one 64-step graph and one graph of the remaining steps, per start buffer;
+ * the graphs are kept until the tile, scheme or context changes.  Runs
+ * nothing on the GPU; errors as mrt_step. */
+int mrt_prepare_steps(mrt_ctx* ctx, int n);
+
 /* Macroscopic fields of the current populations: rho = fhat_1, u = j/rho,
  * T = (e - rho u^2)/(b rho) (R = 1).  Outputs ny*nx doubles on the host
  * (on_device = 0; the call synchronises) or on the device (on_device = 1;
@@ -273,6 +282,8 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
 int mrt_batch_set_fields(mrt_batch* b, int i, const double* rho, const double* ux,
                          const double* uy, const double* T);
 int mrt_batch_step(mrt_batch* b, int n);
+/* As mrt_prepare_steps, for mrt_batch_step. */
+int mrt_batch_prepare_steps(mrt_batch* b, int n);
 /* Moments of instance i to host doubles (any may be NULL).  Synchronises;
  * MRT_EUNSTABLE if any instance went unhealthy. */
 int mrt_batch_read_moments(mrt_batch* b, int i, double* rho, double* ux, double* uy, double* T);

@@ -48,6 +48,10 @@ class Batch:
     def step(self, n: int = 1):
         self._check(L.raw().mrt_batch_step(self._h, int(n)))
 
+    def prepare(self, n: int):
+        """Capture the graphs a following step(n) replays (mrt_batch_prepare_steps)."""
+        self._check(L.raw().mrt_batch_prepare_steps(self._h, int(n)))
+
     def moments(self, i: int):
         c = self.cases[i]
         out = [np.empty((c.ny, c.nx)) for _ in range(4)]

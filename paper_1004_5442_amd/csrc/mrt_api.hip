@@ -171,9 +171,11 @@ struct GraphCache {
     }
 };
 
-// enqueue(cur, stream) launches one step reading buffer cur.
+// enqueue(cur, stream) launches one step reading buffer cur.  launch =
+// false only captures the graphs n steps need (nothing runs, cur is kept).
 template <typename Enqueue>
-hipError_t run_graphs(GraphCache& cache, int& cur, int n, hipStream_t stream, Enqueue enqueue) {
+hipError_t run_graphs(GraphCache& cache, int& cur, int n, hipStream_t stream, Enqueue enqueue,
+                      bool launch = true) {
     auto get = [&](int steps, int start, hipGraphExec_t* out) -> hipError_t {
         const int key = 2 * steps + start;
         auto it = cache.g.find(key);
@@ -209,15 +211,16 @@ hipError_t run_graphs(GraphCache& cache, int& cur, int n, hipStream_t stream, En
     hipGraphExec_t exec = nullptr;
     for (int q = 0; q < n / kGraphChunk; ++q) {
         hipError_t e = get(kGraphChunk, cur, &exec);
-        if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
+        if (e == hipSuccess && launch) e = hipGraphLaunch(exec, stream);
         if (e != hipSuccess) return e;
+        if (!launch) break;      // every replay uses the same graph
     }
     const int r = n % kGraphChunk;
     if (r) {
         hipError_t e = get(r, cur, &exec);
-        if (e == hipSuccess) e = hipGraphLaunch(exec, stream);
+        if (e == hipSuccess && launch) e = hipGraphLaunch(exec, stream);
         if (e != hipSuccess) return e;
-        if (r & 1) cur ^= 1;
+        if (launch && (r & 1)) cur ^= 1;
     }
     return hipSuccess;
 }
@@ -475,7 +478,13 @@ int mrt_set_fields(mrt_ctx* c, const double* rho, const double* ux, const double
     return MRT_OK;
 }
 
-int mrt_step(mrt_ctx* c, int n) {
+static int step_impl(mrt_ctx* c, int n, bool launch);
+
+int mrt_step(mrt_ctx* c, int n) { return step_impl(c, n, true); }
+
+int mrt_prepare_steps(mrt_ctx* c, int n) { return step_impl(c, n, false); }
+
+static int step_impl(mrt_ctx* c, int n, bool launch) {
     if (!c) return MRT_EINVAL;
     std::string& ctx_err = c->err;
     if (n < 0) return ctx_fail(c, MRT_EINVAL, "n < 0");
@@ -500,13 +509,14 @@ int mrt_step(mrt_ctx* c, int n) {
                            c->d_health, c->grid, c->nt, c->walls, st);
     };
     if (n == 1 || c->eager) {
+        if (!launch) return MRT_OK;
         for (int k = 0; k < n; ++k) {
             HIPTRY(enqueue(c->cur, c->stream));
             c->cur ^= 1;
         }
         return MRT_OK;
     }
-    HIPTRY(run_graphs(c->graphs, c->cur, n, c->stream, enqueue));
+    HIPTRY(run_graphs(c->graphs, c->cur, n, c->stream, enqueue, launch));
     return MRT_OK;
 }
 
@@ -976,7 +986,13 @@ int mrt_batch_set_fields(mrt_batch* b, int i, const double* rho, const double* u
     return MRT_OK;
 }
 
-int mrt_batch_step(mrt_batch* b, int n) {
+static int batch_step_impl(mrt_batch* b, int n, bool launch);
+
+int mrt_batch_step(mrt_batch* b, int n) { return batch_step_impl(b, n, true); }
+
+int mrt_batch_prepare_steps(mrt_batch* b, int n) { return batch_step_impl(b, n, false); }
+
+static int batch_step_impl(mrt_batch* b, int n, bool launch) {
     if (!b || n < 0) return MRT_EINVAL;
     std::string& ctx_err = b->err;
     if (n == 0) return MRT_OK;
@@ -990,7 +1006,7 @@ int mrt_batch_step(mrt_batch* b, int n) {
         return mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[cur], b->f[1 - cur],
                            b->d_health, b->grid, b->nt, b->walls, st);
     };
-    HIPTRY(run_graphs(b->graphs, b->cur, n, b->stream, enqueue));
+    HIPTRY(run_graphs(b->graphs, b->cur, n, b->stream, enqueue, launch));
     return MRT_OK;
 }
 

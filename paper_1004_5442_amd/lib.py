@@ -56,6 +56,7 @@ _proto = {
     "mrt_set_params": (c_int, [c_void_p, POINTER(Params)]),
     "mrt_set_fields": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     "mrt_step": (c_int, [c_void_p, c_int]),
+    "mrt_prepare_steps": (c_int, [c_void_p, c_int]),
     "mrt_read_moments": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
     "mrt_get_populations": (c_int, [c_void_p, c_void_p, c_int]),
     "mrt_set_populations": (c_int, [c_void_p, c_void_p, c_int]),
@@ -79,6 +80,7 @@ _proto = {
     "mrt_batch_create": (c_int, [POINTER(c_void_p), c_int, POINTER(Instance), c_int, c_void_p]),
     "mrt_batch_set_fields": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mrt_batch_step": (c_int, [c_void_p, c_int]),
+    "mrt_batch_prepare_steps": (c_int, [c_void_p, c_int]),
     "mrt_batch_read_moments": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mrt_batch_get_populations": (c_int, [c_void_p, c_int, c_void_p]),
     "mrt_batch_set_tile": (c_int, [c_void_p, c_int, c_int]),

@@ -113,6 +113,10 @@ class Solver:
     def step(self, n: int = 1):
         self._check(L.raw().mrt_step(self._h, int(n)))
 
+    def prepare(self, n: int):
+        """Capture the graphs a following step(n) replays (mrt_prepare_steps)."""
+        self._check(L.raw().mrt_prepare_steps(self._h, int(n)))
+
     def sync(self):
         self._check(L.raw().mrt_sync(self._h))
 

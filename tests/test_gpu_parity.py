@@ -114,6 +114,9 @@ def test_graph_replays_equal_plain_launches(precision):
     print(f"case {case.name} {precision} graph replays", flush=True)
     a = solver_for_case(case, precision)    # plain launches
     b = solver_for_case(case, precision)    # graphs
+    before = b.populations()
+    b.prepare(69)                           # captures only: the state is unchanged
+    assert np.array_equal(b.populations(), before)
     for n in (69, 12, 69, 3, 64):
         for _ in range(n):
             a.step(1)
