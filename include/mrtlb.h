@@ -82,7 +82,8 @@ typedef struct mrt_params {
                               s dt up to 1 + 1e-6 is accepted)                  */
     double dt, dx, dy;     /* time step and cell sizes, all > 0                   */
     double eta0;           /* eta on shell 1; the paper fixes 5/2 and so does this
-                              library (any other value: MRT_EINVAL)              */
+                              library: 5/2 or 0 (which selects 5/2); any other
+                              value: MRT_EINVAL                                  */
     double side_state[4][4]; /* (rho, ux, uy, T) of each MRT_BC_EQ side           */
 } mrt_params;
 

@@ -184,3 +184,29 @@ def test_largest_grids_use_the_full_32_bit_offset_range():
                (n // 2, n - 1), (0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1)]
     compare(case, s, centres, NSTEPS, "fp32_eq64")
     s.close()
+
+
+def test_large_grid_with_reflecting_walls_on_every_side():
+    """Above 2^22 cells the reflecting-wall ghosts come from the separate
+    ghost pass (smaller grids write them in the step kernel): a 2048 x 2049
+    2D Riemann grid with reflecting walls on all four sides, sampled at the
+    walls, the corners and the quadrant interfaces after a few steps."""
+    import dataclasses
+    base = W.riemann2d(n=2048, seed=4)
+    rows = 2049
+    pad = lambda a: np.concatenate([a, a[-1:]], axis=0)
+    case = dataclasses.replace(base, name="riemann2d_2048x2049_reflect", ny=rows, rho=pad(base.rho),
+                               ux=pad(base.ux), uy=pad(base.uy), T=pad(base.T),
+                               bc=("reflect",) * 4)
+    assert case.cells > 1 << 22
+    print(f"case {case.name} fp64 ghost pass", flush=True)
+    s = solver_for_case(case, "fp64")
+    s.set_tile(HEADLINE_TILE_ROWS)
+    s.step(NSTEPS)
+    s.sync()
+    nx, ny = case.nx, case.ny
+    centres = [(0, ny // 3), (nx - 1, 2 * ny // 3), (nx // 3, 0), (2 * nx // 3, ny - 1),
+               (0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1), (nx // 2, ny // 2),
+               (nx // 2, 0), (0, ny // 2)]
+    compare(case, s, centres, NSTEPS, "fp64")
+    s.close()

@@ -28,7 +28,8 @@ BC_SETS = [
 
 
 @pytest.mark.parametrize("bc", BC_SETS)
-@pytest.mark.parametrize("shape,rows", [((150, 37), 8), ((64, 5), 2), ((1, 7), 3), ((65, 1), 1)])
+@pytest.mark.parametrize("shape,rows", [((150, 37), 8), ((64, 5), 2), ((1, 7), 3), ((65, 1), 1),
+                                        ((256, 12), 6), ((257, 9), 5), ((512, 3), 6)])
 def test_fp64_populations_match_oracle(bc, shape, rows):
     nx, ny = shape
     case = smooth_case(nx, ny, bc, seed=nx + ny)
