@@ -28,7 +28,7 @@
  *    contiguous), with one ghost cell on each side (-1 <= x <= nx,
  *    -1 <= j <= ny) that the library fills from the boundary conditions as the
  *    step needs it; plane (the sub-row length, a multiple of 256, >= nx + 3),
- *    pitch (= 16 plane) and origin come from mrt_get_layout.  Only these
+ *    pitch (16 plane + 256: a padded row) and origin come from mrt_get_layout.  Only these
  *    three numbers describe the layout: code that indexes with them does not
  *    depend on it.  Velocity order: shell 1 (speed 1) and shell 2
  *    (speed 6) as (+x, +y, -x, -y); shell 3 (sqrt(2)(+-1,+-1)) and shell 4

@@ -56,13 +56,18 @@ size_t elem_size(int prec) { return prec == MRT_FP64 ? 8 : 4; }
 // consecutive sub-rows, one per population, each `sub` elements long (sub a
 // multiple of 256 >= nx + 3, so every sub-row starts 256-byte aligned, the
 // ghost columns x = -1 / x = nx and the never-read column nx + 1 fit in its
-// padding, and a 256-column work item never leaves it).  Population i of
-// cell (x, j) is at origin + j * pitch + i * plane + x with plane = sub and
-// pitch = 16 sub; 64 elements precede the first sub-row.  A block marching up
-// a band then streams one contiguous 16-sub-row stretch per grid row, which
-// the memory system serves faster than 16 streams a plane apart.
+// padding, and a 256-column work item never leaves it), followed by 256
+// elements of padding.  Population i of cell (x, j) is at
+// origin + j * pitch + i * plane + x with plane = sub and pitch = 16 sub + 256;
+// 64 elements precede the first sub-row.  A block marching up a band then
+// streams one contiguous 16-sub-row stretch per grid row, which the memory
+// system serves faster than 16 streams a plane apart.  The padding makes the
+// row stride an odd multiple of 1 KiB (FP32; 2 KiB FP64): with a stride of
+// 2^14 times an integer, bands of 8 or 16 rows start at addresses that
+// concentrate on a few memory channels (measured 10 % slower on 4096^2).
+constexpr long long kRowPad = 256;
 long long sub_for(int nx) { return ((long long)nx + 3 + 255) / 256 * 256; }
-long long pitch_for(int nx) { return 16 * sub_for(nx); }
+long long pitch_for(int nx) { return 16 * sub_for(nx) + kRowPad; }
 long long plane_for(int nx) { return sub_for(nx); }
 long long origin_for(int nx) { return pitch_for(nx) + 64; }
 long long elems_for(int nx, int ny) { return (long long)(ny + 2) * pitch_for(nx) + 512; }

@@ -16,7 +16,7 @@ struct Inst {
     long long off;      // element offset of the instance in the buffers
     long long plane;    // elements between populations (the sub-row length:
                         // a multiple of 256, >= nx + 3)
-    int nx, ny, pitch;  // pitch: elements between grid rows (16 sub-rows)
+    int nx, ny, pitch;  // pitch: elements between grid rows (16 sub-rows + padding)
     int origin;         // population i of cell (x, y) is at
                         // off + i * plane + origin + y * pitch + x for
                         // -1 <= x <= nx, -1 <= y <= ny (x or y outside [0, n):

@@ -25,7 +25,7 @@ if not torch.cuda.is_available():
 
 from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
 
-HEADLINE_TILE_ROWS = 6       # the tile the benchmark runs the 4096^2 grid with
+HEADLINE_TILE_ROWS = 8       # the tile the benchmark runs the 4096^2 grid with
 NSTEPS = 6                   # steps before sampling (window margin = NSTEPS)
 PATCH = 6                    # sampled patch: PATCH x PATCH cells
 

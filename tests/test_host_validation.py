@@ -20,7 +20,7 @@ def _init(nx, ny, prec=2, bc=(0, 0, 0, 0)):
 def test_population_bytes_follow_the_layout():
     for nx, ny, prec in ((1, 1, 0), (300, 7, 2), (4096, 4096, 1)):
         sub = (nx + 3 + 255) // 256 * 256
-        elems = (ny + 2) * 16 * sub + 512
+        elems = (ny + 2) * (16 * sub + 256) + 512
         assert lib.mrt_population_bytes(nx, ny, prec) == elems * (8 if prec == 0 else 4)
     assert lib.mrt_population_bytes(0, 5, 2) == 0
     assert lib.mrt_population_bytes(5, 0, 2) == 0
