@@ -139,6 +139,46 @@ def time_batch(steps, warmup):
             "roofline_frac": round(cells * 128 * steps / sec / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def time_adjoint_large(n, steps):
+    """Adjoint step vs forward step on an n^2 periodic grid of the adjoint
+    workload's kind (FP32 storage, FP64 collision), large enough to leave the
+    caches: the adjoint moves 192 B per site (lam read, f read, lam write)."""
+    import torch
+
+    from paper_1004_5442_amd import workloads as W
+    from paper_1004_5442_amd.solver import Solver
+    case, _ = W.adjoint_problem(n=n, seed=0, nsteps=10)
+    sv = Solver(n, n, "fp32_eq64")
+    # the 256^2 workload's Courant numbers: dt shrinks with the cell size
+    sv.set_params(case.gamma, case.s, case.dt * 256 / n, case.dx, case.dy)
+    rho0 = torch.tensor(case.rho, device="cuda")
+    T0 = torch.tensor(case.T, device="cuda")
+    zero = torch.zeros_like(rho0)
+    f, g = sv.empty_state(), sv.empty_state()
+    sv.init_buffer(rho0, zero, zero, T0, f)
+    lam, lam2 = sv.empty_state(), sv.empty_state()
+    sv.init_buffer(rho0, zero, zero, T0, lam)
+    ds = torch.zeros(16, dtype=torch.float64, device="cuda")
+
+    def fwd(k):
+        for _ in range(k):
+            sv.step_buffers(f, g)
+
+    def adj(k):
+        for _ in range(k):
+            sv.adjoint_step(lam, f, lam2, ds)
+
+    fwd(3)
+    adj(3)
+    st = torch.cuda.current_stream()
+    t_f = _events_time(st, fwd, steps) / steps
+    t_a = _events_time(st, adj, steps) / steps
+    sv.close()
+    return {"grid": f"{n}x{n}", "adjoint_step_ms": round(1e3 * t_a, 4), "forward_step_ms": round(1e3 * t_f, 4),
+            "adjoint_over_forward": round(t_a / t_f, 3), "adjoint_mlups": round(n * n / t_a / 1e6, 1),
+            "adjoint_roofline_frac": round(n * n * 192 / t_a / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def time_adjoint(steps):
     """Adjoint step vs forward step on the 256^2 periodic adjoint workload
     (FP32 storage, FP64 collision), and one full gradient (500-step forward,
@@ -329,6 +369,7 @@ def main():
                 "note": "36,000 cells: launch-latency bound (captured graphs of 64 steps)"}
         extra["batched_512_tubes"] = time_batch(max(50, args.steps // 2), 5)
         extra["adjoint_256"] = time_adjoint(100)
+        extra["adjoint_2048"] = time_adjoint_large(2048, 20)
         out["extra"] = extra
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
