@@ -23,6 +23,8 @@ hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, i
                    hipStream_t st);
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                   void* fout, unsigned* health, int grid, bool nt, bool walls, hipStream_t st);
+hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
+                   void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
 hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool reflect,
                      const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
@@ -243,6 +245,11 @@ void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
 // Short bands (at most 6 rows) and many blocks: the step streams best with
 // ~8-16k blocks of short marches (measured on the 4096^2 grid); small grids
 // go down to one-row bands so that they still spread over the chip.
+// Default band height of the two-step kernel: each band recomputes f^{n+1}
+// on two extra rows, so taller bands waste less (1/rows) but give fewer
+// blocks.
+constexpr int kDefaultRows2 = 16;
+
 int default_rows(int nx, int ny) {
     const long long chunks = (nx + 255) / 256;
     long long r = (chunks * ny + 8191) / 8192;
@@ -276,6 +283,10 @@ struct mrt_ctx {
     bool nt = false;                 // non-temporal population stores (large grids)
     bool walls = false;              // the step kernel writes the reflecting-wall ghosts
     GraphCache graphs;               // captured steps of mrt_step
+    int per_pass = 1;                // time steps per pass of the marching kernel (1 or 2)
+    Item* d_items2 = nullptr;        // work items of the two-step kernel
+    int nitems2 = 0, rows2 = 0;
+    GraphCache graphs2;              // captured two-step passes
     bool eager = false;              // launch step by step (the tile autotuner)
     int scheme = 0;                  // MRT_SCHEME_* flags
     void* f_tmp = nullptr;           // post-collision state of the split scheme
@@ -322,6 +333,21 @@ int build_items(mrt_ctx* c, int rows) {
     c->nitems = int(items.size());
     c->rows = rows;
     c->graphs.clear();
+    return MRT_OK;
+}
+
+// Work items of the two-step kernel: bands of `rows` <= 32 rows.
+int build_items2(mrt_ctx* c, int rows) {
+    std::string& ctx_err = c->err;
+    std::vector<Item> items;
+    add_items(items, 0, c->nx, c->ny, rows);
+    if (c->d_items2) HIPTRY(hipFree(c->d_items2));
+    c->d_items2 = nullptr;
+    HIPTRY(hipMalloc(&c->d_items2, items.size() * sizeof(Item)));
+    HIPTRY(hipMemcpy(c->d_items2, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    c->nitems2 = int(items.size());
+    c->rows2 = rows;
+    c->graphs2.clear();
     return MRT_OK;
 }
 
@@ -501,6 +527,46 @@ static int step_impl(mrt_ctx* c, int n, bool launch) {
     // step.  The per-cell nine-point kernel writes none, so its ghosts
     // (corners too) are always refilled (the split scheme refills those of
     // its post-collision state itself)
+    if (c->per_pass == 2 && c->scheme == 0) {
+        // two steps per pass; an odd last step by the single-step kernel.
+        // Neither writes the reflecting-wall ghosts of its output here: the
+        // ghost pass refreshes them before every launch
+        auto enqueue2 = [&](int cur, hipStream_t st) -> hipError_t {
+            if (reflect) {
+                const hipError_t e = mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[cur], 1, st);
+                if (e != hipSuccess) return e;
+            }
+            return mrt::k_step2(c->prec, c->d_inst, c->d_items2, c->nitems2, c->f[cur], c->f[1 - cur],
+                                c->d_health, 0, c->nt, st);
+        };
+        auto enqueue1 = [&](int cur, hipStream_t st) -> hipError_t {
+            if (reflect) {
+                const hipError_t e = mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[cur], 1, st);
+                if (e != hipSuccess) return e;
+            }
+            return mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[cur], c->f[1 - cur],
+                               c->d_health, c->grid, c->nt, false, st);
+        };
+        const int pairs = n / 2;
+        if (c->eager || pairs == 1) {
+            if (launch && pairs == 1) {
+                HIPTRY(enqueue2(c->cur, c->stream));
+                c->cur ^= 1;
+            }
+            if (launch && c->eager)
+                for (int k = 1; k < pairs; ++k) {
+                    HIPTRY(enqueue2(c->cur, c->stream));
+                    c->cur ^= 1;
+                }
+        } else if (pairs > 1) {
+            HIPTRY(run_graphs(c->graphs2, c->cur, pairs, c->stream, enqueue2, launch));
+        }
+        if ((n & 1) && launch) {
+            HIPTRY(enqueue1(c->cur, c->stream));
+            c->cur ^= 1;
+        }
+        return MRT_OK;
+    }
     const bool ghost_pass = reflect && (c->scheme == MRT_SCHEME_LW_CROSS || (c->scheme == 0 && !c->walls));
     auto enqueue = [&](int cur, hipStream_t st) -> hipError_t {
         if (ghost_pass) {
@@ -618,6 +684,33 @@ int mrt_set_tile(mrt_ctx* c, int rows, int grid) {
     return MRT_OK;
 }
 
+int mrt_set_steps_per_pass(mrt_ctx* c, int steps, int rows) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (steps != 1 && steps != 2) return ctx_fail(c, MRT_EINVAL, "steps per pass: 1 or 2");
+    if (rows < 0 || rows > MRT_MAX_BAND_ROWS_2) return ctx_fail(c, MRT_EINVAL, "rows: 0 (default) to 32");
+    if (steps == 2 && c->prec == MRT_FP64)
+        return ctx_fail(c, MRT_EINVAL, "two steps per pass need FP32 storage");
+    if (steps == 2) {
+        const int r = std::min(rows > 0 ? rows : kDefaultRows2, c->ny);
+        if (r != c->rows2 || !c->d_items2) {
+            const int rc = build_items2(c, r);
+            if (rc != MRT_OK) return rc;
+        }
+    }
+    c->per_pass = steps;
+    c->graphs.clear();
+    c->graphs2.clear();
+    // the two-step path leaves the reflecting ghosts of the current state
+    // stale; the single-step kernel expects them current
+    if (c->params_set && c->fields_set) {
+        const int rc = fill_ghosts(c);
+        if (rc != MRT_OK) return rc;
+    }
+    HIPTRY(hipStreamSynchronize(c->stream));
+    return MRT_OK;
+}
+
 int mrt_set_scheme(mrt_ctx* c, int flags) {
     if (!c) return MRT_EINVAL;
     std::string& ctx_err = c->err;
@@ -712,8 +805,10 @@ void mrt_destroy(mrt_ctx* c) {
     if (c->d_inst) (void)hipFree(c->d_inst);
     if (c->d_items) (void)hipFree(c->d_items);
     if (c->d_items_adj) (void)hipFree(c->d_items_adj);
+    if (c->d_items2) (void)hipFree(c->d_items2);
     if (c->f_tmp) (void)hipFree(c->f_tmp);
     c->graphs.clear();
+    c->graphs2.clear();
     if (c->d_stage) (void)hipFree(c->d_stage);
     if (c->d_partial) (void)hipFree(c->d_partial);
     if (c->d_health) (void)hipFree(c->d_health);

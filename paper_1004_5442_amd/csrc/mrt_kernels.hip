@@ -90,8 +90,8 @@ __device__ __forceinline__ void conserved_compensated(const float f[16], float q
 
 // dt * C for one cell in precision C (see collision_dt), converted to the
 // storage type; COMP replaces the conserved moments by compensated FP32 sums.
-template <typename C, bool COMP, typename S>
-__device__ __forceinline__ void cell_collision(const S fs[16], C b, C binv, const double* sdt,
+template <typename C, bool COMP, typename S, typename DP>
+__device__ __forceinline__ void cell_collision(const S fs[16], C b, C binv, DP sdt,
                                                S out[16], C& rho, C& P) {
     C f[16], m[16], eq[16], dm[16], o[16];
 #pragma unroll
@@ -117,14 +117,39 @@ template <typename S>
 struct Weights;
 template <>
 struct Weights<float> {
-    __device__ static float get(const Inst* P, int ax, int k, int j) { return P->lwf[ax][k][j]; }
+    template <typename IP>
+    __device__ static float get(IP P, int ax, int k, int j) { return P->lwf[ax][k][j]; }
     __device__ static float cross(const Inst* P, int k) { return P->lwcf[k]; }
 };
 template <>
 struct Weights<double> {
-    __device__ static double get(const Inst* P, int ax, int k, int j) { return P->lw[ax][k][j]; }
+    template <typename IP>
+    __device__ static double get(IP P, int ax, int k, int j) { return P->lw[ax][k][j]; }
     __device__ static double cross(const Inst* P, int k) { return P->lwc[k]; }
 };
+
+// New value of population i of a site: f + LW_i(f) - dt C_i, with the
+// neighbour values W / E (x - 1 / x + 1; used if population i moves in x)
+// and So / N (y - 1 / y + 1; used if it moves in y).  The Lax-Wendroff
+// increment d = sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x)) is
+// formed as w_down f(x+e) + w_up f(x-e) - c^2 f(x) (the terms cancel to d;
+// every rounding is c times smaller than f).
+template <typename S, typename IP>
+__device__ __forceinline__ S site_update(IP P, int i, S f, S W, S E, S So, S N, S cdt) {
+    const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
+    S d = S(0);
+    if (sx != 0) {
+        const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
+        const S we = sx > 0 ? wd : wu, ww = sx > 0 ? wu : wd;
+        d = we * E + (ww * W - (wd + wu) * f);
+    }
+    if (sy != 0) {
+        const S wd = Weights<S>::get(P, 1, k, 0), wu = Weights<S>::get(P, 1, k, 1);
+        const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
+        d += wn * N + (ws * So - (wd + wu) * f);
+    }
+    return f + (d - cdt);
+}
 
 // ------------------------------------------------------------------ ghosts
 
@@ -243,7 +268,8 @@ __global__ __launch_bounds__(256) void ghost_kernel(const Inst* __restrict__ ins
 // offset in a plane of row y, -1 <= y <= ny, with the boundary remap
 // (unsigned arithmetic: r = -1 wraps to origin - pitch; the library keeps
 // every instance below 2^32 elements, so the offset itself never wraps)
-__device__ __forceinline__ unsigned row_offset(const Inst* __restrict__ P, int y) {
+template <typename IP>
+__device__ __forceinline__ unsigned row_offset(IP P, int y) {
     const int r = y < 0 ? P->row_lo : (y >= P->ny ? P->row_hi : y);
     return unsigned(P->origin) + unsigned(r) * unsigned(P->pitch);
 }
@@ -353,29 +379,14 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
         if (act && !(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
-            // increment d = sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x)),
-            // formed as w_down f(x+e) + w_up f(x-e) - c^2 f(x) (the terms
-            // cancel to d; every rounding is c times smaller than f)
-            S d = S(0);
-            if (sx != 0) {
-                const S W = from_left(r0[i], h[i]);
-                const S E = from_right(r0[i], h[i]);
-                const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
-                const S we = sx > 0 ? wd : wu, ww = sx > 0 ? wu : wd;
-                d = we * E + (ww * W - (wd + wu) * r0[i]);
-            }
-            if (sy != 0) {
-                const S wd = Weights<S>::get(P, 1, k, 0), wu = Weights<S>::get(P, 1, k, 1);
-                const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
-                d += wn * rp[i] + (ws * rm[i] - (wd + wu) * r0[i]);
-            }
+            const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
+            const S E = moves_x(i) ? from_right(r0[i], h[i]) : S(0);
             // NT (grids far larger than the last-level cache): non-temporal
             // stores, so the new rows do not displace the halo rows that
             // other blocks still read; smaller grids keep them cached for
             // the next step
             S* dst = &(fo + (long long)i * plane)[o + xs];
-            const S v = r0[i] + (d - cdt[i]);
+            const S v = site_update(P, i, r0[i], W, E, rm[i], rp[i], cdt[i]);
             if constexpr (NT)
                 __builtin_nontemporal_store(v, dst);
             else
@@ -407,11 +418,15 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
             }
             if (ref_xwave) {
                 reflected_eq<C>(v, 0, b, binv, g);
-                if (ref_w || ref_e) {
-                    // column -1 or nx of this row (32-bit sum: o >= 64)
-                    const unsigned gx = ref_w ? o - 1u : o + unsigned(nx);
+                // column -1 and / or nx of this row (both on a one-column
+                // grid; 32-bit sums: o >= 64)
+                if (ref_w) {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[gx] = g[i];
+                    for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[o - 1u] = g[i];
+                }
+                if (ref_e) {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[o + unsigned(nx)] = g[i];
                 }
             }
         }
@@ -469,6 +484,333 @@ __global__ __launch_bounds__(256, (step_waves<S, COMP, WALLS>())) void step_kern
         const Item it = items[w];
         step_block<S, C, COMP, NT, WALLS>(insts + it.inst, it.x0, it.y0, it.y1, fin, fout, health, lds);
         __syncthreads();   // the next item reuses the edge buffer
+    }
+}
+
+// ---------------------------------------------------------------- two steps
+
+// Two time steps per pass over the populations (temporal blocking), FP32
+// storage.  The single-step kernel moves 128 B per site update and is bound
+// by HBM; here a block reads f^n once, keeps f^{n+1} in registers only and
+// writes f^{n+2}: half the memory traffic per step for a little recomputation
+// at the band edges.  A work item is 256 columns [x0, x0 + 256) of rows
+// [y0, y1), y1 - y0 <= kBand2; the block marches rows y = y0 - 1 .. y1 and
+// at row y
+//  * computes f^{n+1} of row y from the f^n window (rows y-1, y, y+1; the
+//    single-step arithmetic, x neighbours by DPP / LDS / the two halo-column
+//    loads, row y + 2 prefetched), the halo rows y0 - 1 and y1 included;
+//  * computes f^{n+2} of row y - 1 from the f^{n+1} window (rows y-2, y-1,
+//    y) and stores it (y0 < y <= y1).
+// The x neighbours of f^{n+1} outside the block (columns x0 - 1 and
+// min(x0 + 256, nx)) are computed before the march by wave 0, one lane per
+// row and side (cell_update), and kept in LDS.  Boundaries at the
+// intermediate level follow the same rules as a stored state: periodic sides
+// are computed at the wrapped cell (rows -2 / ny + 1 are read through a
+// two-deep wrap), outflow, reflecting and fixed-equilibrium ghosts are the
+// adjacent f^{n+1} cell, its reflection, and the side's equilibrium.  The
+// f^{n+2} ghost ring is refilled by the ghost pass before the next launch.
+constexpr int kBand2 = 32;
+
+// The instance pointer made opaque to the compiler, so that the parameters
+// read through it (rates, Lax-Wendroff weights) are loaded again where they
+// are used instead of being held in scalar registers across the whole march
+// (which spills them to vector-register lanes); as a constant-address-space
+// pointer, so that the loads stay scalar.
+using ConstInst = const __attribute__((address_space(4))) Inst;
+using ConstItem = const __attribute__((address_space(4))) Item;
+__device__ __forceinline__ ConstInst* reload(ConstInst* p) {
+    unsigned long long a = reinterpret_cast<unsigned long long>(p);
+    asm volatile("" : "+s"(a));
+    return reinterpret_cast<ConstInst*>(a);
+}
+
+template <typename S>
+struct EdgeBuf2 {
+    S v[2][2][kWaves][2][12];      // [slot][level][wave][lane 0 / 63][x-moving population]
+    S halo[2][kBand2][12];         // [west / east][row - y0]: f^{n+1} of the halo columns
+};
+
+// f^{n+1} of the grid cell (sx, y), 0 <= sx < nx, 0 <= y < ny, from f^n
+// with the neighbours through the one-deep remap (one lane's single step).
+template <typename S, typename C, bool COMP>
+__device__ void cell_update(ConstInst* __restrict__ P, const S* __restrict__ fi, int sx, int y,
+                            C b, C binv, S out[16]) {
+    const long long plane = P->plane;
+    const unsigned o = row_offset(P, y), om = row_offset(P, y - 1), op = row_offset(P, y + 1);
+    const unsigned c = unsigned(sx);
+    const unsigned cw = unsigned(sx > 0 ? sx - 1 : P->col_lo);
+    const unsigned ce = unsigned(sx + 1 < P->nx ? sx + 1 : P->col_hi);
+    auto ld = [&](int i, unsigned row, unsigned col) -> S {
+        return (fi + (long long)i * plane)[row + col];
+    };
+    S f[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = ld(i, o, c);
+    S cdt[16];
+    C rho, Pp;
+    cell_collision<C, COMP>(f, b, binv, P->sdt, cdt, rho, Pp);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const S W = moves_x(i) ? ld(i, o, cw) : S(0);
+        const S E = moves_x(i) ? ld(i, o, ce) : S(0);
+        const S So = moves_y(i) ? ld(i, om, c) : S(0);
+        const S N = moves_y(i) ? ld(i, op, c) : S(0);
+        out[i] = site_update(P, i, f[i], W, E, So, N, cdt[i]);
+    }
+}
+
+// The f^{n+1} ghost row of a non-periodic y side from the adjacent row
+// `v` (fixed equilibrium, outflow copy, or reflection).
+template <typename S, typename C>
+__device__ __forceinline__ void ghost_row_rule(ConstInst* __restrict__ P, int side, const S (&v)[16],
+                                               C b, C binv, S (&g)[16]) {
+    const int kind = P->bc[side];
+    if (kind == BC_EQ) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[side][i]);
+    } else if (kind == BC_REFLECT) {
+        reflected_eq<C>(v, 1, b, binv, g);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g[i] = v[i];
+    }
+}
+
+template <typename S, typename C, bool COMP, bool NT>
+__device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, int y0, int y1,
+                                            const S* __restrict__ fin, S* __restrict__ fout,
+                                            unsigned* __restrict__ health, EdgeBuf2<S>& lds) {
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long plane = P->plane;
+    const S* __restrict__ fi = fin + P->off;
+    S* __restrict__ fo = fout + P->off;
+    const int nx = P->nx, ny = P->ny;
+    const int x = x0 + 64 * wv + lane;
+    const bool act = x < nx;
+    const unsigned cx = unsigned(act ? x : P->col_hi);
+    const unsigned xs = unsigned(act ? x : nx + 1);
+    const C b = C(P->b), binv = C(P->binv);
+    auto ld = [&](int i, unsigned row, unsigned col) -> S {
+        return (fi + (long long)i * plane)[row + col];
+    };
+    const bool west = wv == 0 && lane == 0, east = wv == kWaves - 1 && lane == 63;
+    const bool hmem = west || east;
+    unsigned hx = cx;
+    if (west) hx = unsigned(x0 > 0 ? x0 - 1 : P->col_lo);
+    if (east) hx = unsigned(x0 + 256 < nx ? x0 + 256 : P->col_hi);
+    const bool edge_lane = lane == 0 || lane == 63;
+    const int eside = lane == 0 ? 0 : 1;
+    const int nwave = lane == 0 ? wv - 1 : wv + 1;
+    const int nside = lane == 0 ? 1 : 0;
+    const bool hlds = edge_lane && !hmem;
+    // east f^{n+1} neighbour of the last grid column when it lies inside a
+    // wave (the DPP shift would bring the value of a lane past the grid)
+    const int xe = x0 + 256 < nx ? x0 + 256 : nx;
+    const bool east_mid = x == xe - 1 && !east;
+    const bool per_lo = P->bc[YLO] == BC_PERIODIC, per_hi = P->bc[YHI] == BC_PERIODIC;
+    // row offsets from values read once per item (the march reads the
+    // instance only through reload(); periodic sides wrap two rows deep,
+    // other sides go through the one-deep remap: rows -2 / ny + 1 are then
+    // read only for values the boundary rule replaces)
+    const unsigned origin = unsigned(P->origin), pitch = unsigned(P->pitch);
+    const int row_lo = P->row_lo, row_hi = P->row_hi;
+    auto roff = [&](int y) -> unsigned {
+        const int r = y < 0 ? row_lo : (y >= ny ? row_hi : y);
+        return origin + unsigned(r) * pitch;
+    };
+    auto roff2 = [&](int y) -> unsigned {
+        int r = y;
+        if (y < 0) {
+            if (per_lo) {
+                r = y + ny;
+                if (r < 0) r += ny;
+            } else {
+                r = row_lo;
+            }
+        } else if (y >= ny) {
+            if (per_hi) {
+                r = y - ny;
+                if (r >= ny) r -= ny;
+            } else {
+                r = row_hi;
+            }
+        }
+        return origin + unsigned(r) * pitch;
+    };
+
+    auto publish = [&](const S (&r)[16], int slot, int level) {
+        if (edge_lane) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (moves_x(i)) lds.v[slot][level][wv][eside][xslot(i)] = r[i];
+        }
+    };
+
+    // f^{n+1} of the halo columns, rows [y0, y1): lanes 0-31 west, 32-63 east
+    if (wv == 0) {
+        const int side = lane >> 5, r = lane & 31, y = y0 + r;
+        if (y < y1) {
+            const int hc = side == 0 ? x0 - 1 : xe;
+            const int bside = side == 0 ? XLO : XHI;
+            int src = hc, rule = 0;          // 0: f^{n+1}(src); 1: its reflection; 2: equilibrium
+            if (hc < 0 || hc >= nx) {
+                const int kind = P->bc[bside];
+                if (kind == BC_PERIODIC) {
+                    src = side == 0 ? nx - 1 : 0;
+                } else if (kind == BC_EQ) {
+                    rule = 2;
+                } else {
+                    src = side == 0 ? 0 : nx - 1;
+                    rule = kind == BC_REFLECT ? 1 : 0;
+                }
+            }
+            S g[16];
+            if (rule == 2) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[bside][i]);
+            } else {
+                S u[16];
+                cell_update<S, C, COMP>(P, fi, src, y, b, binv, u);
+                if (rule == 1) {
+                    reflected_eq<C>(u, 0, b, binv, g);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) g[i] = u[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (moves_x(i)) lds.halo[side][r][xslot(i)] = g[i];
+        }
+    }
+
+    // rm, r0, rp, rn: f^n rows y-1, y, y+1, y+2 (prefetched);
+    // q2, q1, qn: f^{n+1} rows y-2, y-1, y (qn computed here)
+    auto body = [&](const S (&rm)[16], const S (&r0)[16], const S (&rp)[16], S (&rn)[16],
+                    const S (&q2)[16], S (&q1)[16], S (&qn)[16], int y) {
+        const bool more = y < y1;
+        if (more) {
+            const unsigned on = roff2(y + 2);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) rn[i] = ld(i, on, cx);
+        }
+        // f^{n+1}, row y
+        {
+            ConstInst* __restrict__ Pc = reload(P);
+            const unsigned o = roff2(y);
+            S h[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) h[i] = S(0);
+            if (hmem) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) h[i] = ld(i, o, hx);
+            } else if (hlds) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) h[i] = lds.v[y & 1][0][nwave][nside][xslot(i)];
+            }
+            S cdt[16];
+            C rho, Pp;
+            cell_collision<C, COMP>(r0, b, binv, Pc->sdt, cdt, rho, Pp);
+            if (act && y >= 0 && y < ny && !(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
+                const S E = moves_x(i) ? from_right(r0[i], h[i]) : S(0);
+                qn[i] = site_update(Pc, i, r0[i], W, E, rm[i], rp[i], cdt[i]);
+            }
+        }
+        // ghost rows of f^{n+1} on non-periodic y sides
+        if (y == 0 && !per_lo) ghost_row_rule<S, C>(P, YLO, qn, b, binv, q1);
+        if (y == ny && !per_hi) ghost_row_rule<S, C>(P, YHI, q1, b, binv, qn);
+        // f^{n+2}, row y - 1
+        if (y > y0) {
+            ConstInst* __restrict__ Pc = reload(P);
+            const int r = y - 1 - y0;
+            S h[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) h[i] = S(0);
+            if (hmem) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) h[i] = lds.halo[west ? 0 : 1][r][xslot(i)];
+            } else if (hlds) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) h[i] = lds.v[(y - 1) & 1][1][nwave][nside][xslot(i)];
+            }
+            S cdt[16];
+            C rho, Pp;
+            cell_collision<C, COMP>(q1, b, binv, Pc->sdt, cdt, rho, Pp);
+            if (act && !(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
+            const unsigned o = roff(y - 1);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const S W = moves_x(i) ? from_left(q1[i], h[i]) : S(0);
+                S E = moves_x(i) ? from_right(q1[i], h[i]) : S(0);
+                if (moves_x(i) && east_mid) E = lds.halo[1][r][xslot(i)];
+                S* dst = &(fo + (long long)i * plane)[o + xs];
+                const S v = site_update(Pc, i, q1[i], W, E, q2[i], qn[i], cdt[i]);
+                if constexpr (NT)
+                    __builtin_nontemporal_store(v, dst);
+                else
+                    *dst = v;
+            }
+        }
+        // hand the edge values of f^n row y+1 and f^{n+1} row y to the
+        // neighbour waves
+        if (more) {
+            publish(rp, (y + 1) & 1, 0);
+            publish(qn, y & 1, 1);
+        }
+        __syncthreads();
+    };
+
+    S A[16], B[16], Cw[16], D[16], E[16], F[16], G[16], H[16];
+    {
+        const unsigned om = roff2(y0 - 2), o0 = roff2(y0 - 1), op = roff2(y0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            A[i] = moves_y(i) ? ld(i, om, cx) : S(0);
+            B[i] = ld(i, o0, cx);
+            Cw[i] = ld(i, op, cx);
+            D[i] = E[i] = F[i] = G[i] = H[i] = S(0);
+        }
+    }
+    publish(B, (y0 - 1) & 1, 0);
+    __syncthreads();
+    // four register sets per level rotate, so no copies between rows
+    for (int y = y0 - 1; y <= y1;) {
+        body(A, B, Cw, D, G, H, E, y); ++y;
+        if (y > y1) break;
+        body(B, Cw, D, A, H, E, F, y); ++y;
+        if (y > y1) break;
+        body(Cw, D, A, B, E, F, G, y); ++y;
+        if (y > y1) break;
+        body(D, A, B, Cw, F, G, H, y); ++y;
+    }
+}
+
+template <typename S, typename C, bool COMP, bool NT>
+__global__ __launch_bounds__(256) void step2_kernel(const Inst* __restrict__ insts,
+                                                    const Item* __restrict__ items, int nitems,
+                                                    const S* __restrict__ fin, S* __restrict__ fout,
+                                                    unsigned* __restrict__ health) {
+    __shared__ EdgeBuf2<S> lds;
+    // the instance and item tables do not change during the launch: read
+    // them through the constant address space (scalar loads)
+    ConstInst* cinsts = (ConstInst*)insts;
+    ConstItem* citems = (ConstItem*)items;
+    // XCD-aware item order as in step_kernel
+    const int per = (nitems + 7) >> 3;
+    for (int q = blockIdx.x; q < 8 * per; q += gridDim.x) {
+        const int w = (q & 7) * per + (q >> 3);
+        if (w >= nitems) continue;
+        const int inst = citems[w].inst, x0 = citems[w].x0, y0 = citems[w].y0, y1 = citems[w].y1;
+        step2_block<S, C, COMP, NT>(cinsts + inst, x0, y0, y1, fin, fout, health, lds);
+        __syncthreads();   // the next item reuses the LDS buffers
     }
 }
 
@@ -859,6 +1201,20 @@ hipError_t launch_step(const Inst* insts, const Item* items, int nitems, const v
     return hipGetLastError();
 }
 
+template <typename S, typename C, bool COMP>
+hipError_t launch_step2(const Inst* insts, const Item* items, int nitems, const void* fin,
+                        void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = grid > 0 ? grid : 8 * ((nitems + 7) / 8);
+    if (nt)
+        hipLaunchKernelGGL((step2_kernel<S, C, COMP, true>), dim3(blocks), dim3(256), 0, st, insts,
+                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+    else
+        hipLaunchKernelGGL((step2_kernel<S, C, COMP, false>), dim3(blocks), dim3(256), 0, st, insts,
+                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+    return hipGetLastError();
+}
+
 }  // namespace mrt
 
 // Entry points used by the host library (mrt_api.hip); precision codes as in
@@ -892,6 +1248,17 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
         case 0: return launch_step<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, walls, st);
         case 1: return launch_step<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, walls, st);
         default: return launch_step<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, walls, st);
+    }
+}
+
+// Two steps from fin to fout (FP32 storage forms only; bands of at most
+// kBand2 rows); the reflecting-wall ghosts of fin must be current.
+hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
+                   void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+    switch (prec) {
+        case 1: return launch_step2<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        case 2: return launch_step2<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        default: return hipErrorInvalidValue;
     }
 }
 

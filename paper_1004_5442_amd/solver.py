@@ -146,6 +146,11 @@ class Solver:
         flags = (L.SCHEME_SPLIT if split else 0) | (L.SCHEME_LW_CROSS if lw_cross else 0)
         self._check(L.raw().mrt_set_scheme(self._h, flags))
 
+    def set_steps_per_pass(self, steps: int, rows: int = 0):
+        """1 or 2 time steps per kernel pass (mrt_set_steps_per_pass); rows:
+        band height of the two-step kernel (0: default)."""
+        self._check(L.raw().mrt_set_steps_per_pass(self._h, int(steps), int(rows)))
+
     def set_tile(self, rows: int, grid: int = 0):
         self._check(L.raw().mrt_set_tile(self._h, int(rows), int(grid)))
 

@@ -24,6 +24,7 @@ BC_SETS = [
     ("eq", "outflow", "reflect", "reflect"),
     ("reflect", "eq", "periodic", "periodic"),
     ("outflow", "reflect", "eq", "outflow"),
+    ("reflect", "reflect", "reflect", "reflect"),
 ]
 
 

@@ -1,0 +1,173 @@
+"""GPU parity of the two-steps-per-pass kernel (mrt_set_steps_per_pass).
+
+One launch advances the state two steps: f^{n+1} lives only in registers
+(FP32, as the single-step kernel would store it), recomputed on the two halo
+rows of each band and on the two halo columns of each block, with the
+boundary rules applied to it in the kernel.  Against the FP64 oracle (the
+stated 1e-5 on rho, u, T) and against the single-step kernel on the same
+input (which rounds f^{n+1} to FP32 the same way: agreement to a few FP32
+ulps), on ragged shapes, every boundary kind on every side, band heights
+from 1 to 32 rows, odd step counts (a single step ends the run), graph
+replays, and the 4096^2 shock-bubble grid at the benchmark's configuration.
+"""
+import numpy as np
+import pytest
+
+from helpers import field_errors, oracle_params, oracle_run, smooth_case
+from oracle import mrt
+from paper_1004_5442_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
+
+BC_SETS = [
+    ("periodic", "periodic", "periodic", "periodic"),
+    ("reflect", "reflect", "reflect", "reflect"),
+    ("eq", "outflow", "reflect", "reflect"),
+    ("reflect", "eq", "periodic", "periodic"),
+    ("outflow", "reflect", "eq", "outflow"),
+    ("periodic", "periodic", "reflect", "eq"),
+]
+SHAPES = [((150, 37), 8), ((64, 5), 2), ((1, 7), 3), ((65, 1), 1), ((256, 12), 5),
+          ((257, 9), 32), ((512, 3), 1), ((300, 40), 32), ((2, 2), 1)]
+
+
+def close_to_single_step(a, b):
+    """populations of the two paths: equal up to a few FP32 roundings"""
+    scale = np.abs(b).max()
+    return float(np.max(np.abs(a - b)) / scale)
+
+
+@pytest.mark.parametrize("bc", BC_SETS)
+@pytest.mark.parametrize("shape,rows", SHAPES)
+def test_two_step_matches_oracle_and_single_step(bc, shape, rows):
+    nx, ny = shape
+    nsteps = 13                     # six two-step passes and one single step
+    case = smooth_case(nx, ny, bc, seed=3 * nx + ny)
+    print(f"case {case.name} bc={bc} rows={rows} fp32_eq64 two-step", flush=True)
+    want, p = oracle_run(case, nsteps)
+    one = solver_for_case(case, "fp32_eq64")
+    one.step(nsteps)
+    two = solver_for_case(case, "fp32_eq64")
+    two.set_steps_per_pass(2, rows)
+    two.step(nsteps)
+    err = field_errors(two.moments(), mrt.macroscopic(want, p.b))
+    d = close_to_single_step(two.populations(), one.populations())
+    print("vs oracle", err, "vs single step", d, flush=True)
+    assert max(err.values()) < 1e-5, err
+    assert d < 1e-6, d
+    one.close()
+    two.close()
+
+
+@pytest.mark.parametrize("bc", BC_SETS[1:3])
+def test_pure_fp32_form_two_step(bc):
+    case = smooth_case(300, 40, bc, seed=5)
+    print(f"case {case.name} bc={bc} fp32 two-step", flush=True)
+    want, p = oracle_run(case, 40)
+    s = solver_for_case(case, "fp32")
+    s.set_steps_per_pass(2, 16)
+    s.step(40)
+    err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+    print("fp32 two-step", err, flush=True)
+    assert max(err.values()) < 1e-5, err
+    s.close()
+
+
+def test_graph_replays_and_switching_back():
+    """Many passes through captured graphs (64-pass chunks plus remainders),
+    odd counts, then back to one step per pass (the reflecting ghosts of the
+    current state are refreshed by the switch) and forth again."""
+    case = smooth_case(300, 40, ("reflect", "eq", "reflect", "outflow"), seed=21)
+    print(f"case {case.name} two-step graphs", flush=True)
+    total = 0
+    s = solver_for_case(case, "fp32_eq64")
+    s.set_steps_per_pass(2, 8)
+    for n in (129, 2, 7):
+        s.step(n)
+        total += n
+    s.set_steps_per_pass(1, 0)
+    s.step(5)
+    total += 5
+    s.set_steps_per_pass(2, 0)
+    s.step(64)
+    total += 64
+    want, p = oracle_run(case, total)
+    err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+    print(total, "steps", err, flush=True)
+    assert max(err.values()) < 1e-5, err
+    s.close()
+
+
+def test_health_flag_in_two_step_pass():
+    from paper_1004_5442_amd.lib import UnstableError
+    case = smooth_case(70, 9, BC_SETS[0])
+    s = solver_for_case(case, "fp32_eq64")
+    s.set_steps_per_pass(2, 0)
+    f = s.populations()
+    f[:, 4, 33] = np.nan
+    s.set_populations(f)
+    s.step(2)
+    with pytest.raises(UnstableError):
+        s.moments()
+    s.close()
+
+
+def test_rejected_settings():
+    from paper_1004_5442_amd.lib import MRTError
+    case = smooth_case(64, 5, BC_SETS[0])
+    s = solver_for_case(case, "fp64")
+    with pytest.raises(MRTError):
+        s.set_steps_per_pass(2, 0)              # FP64 storage
+    s.close()
+    s = solver_for_case(case, "fp32_eq64")
+    for steps, rows in ((3, 0), (0, 0), (2, 33), (2, -1)):
+        with pytest.raises(MRTError):
+            s.set_steps_per_pass(steps, rows)
+    s.set_steps_per_pass(2, 32)                 # accepted: clamped to the 5 rows
+    s.step(4)
+    s.close()
+
+
+def test_variants_run_one_step_per_pass():
+    """A scheme variant ignores the two-step setting (its own kernels)."""
+    case = smooth_case(150, 37, ("eq", "outflow", "reflect", "reflect"), seed=2)
+    want, p = oracle_run(case, 6, split=True)
+    s = solver_for_case(case, "fp32_eq64")
+    s.set_steps_per_pass(2, 0)
+    s.set_scheme(split=True)
+    s.step(6)
+    err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+    assert max(err.values()) < 1e-5, err
+    s.close()
+
+
+def test_shock_bubble_4096_two_step_sampled():
+    """The benchmark grid (FP32 storage, non-temporal stores, 16-row bands):
+    7 steps (three passes and a single step), then patches at the shock, the
+    bubble, the walls, inflow, outflow and the corners against the oracle's
+    windowed evaluation, and the whole state against the single-step path."""
+    from test_gpu_fullsize import compare, shock_bubble_centres
+    n, nsteps = 4096, 7
+    case = W.shock_bubble(n=n)
+    print(f"case {case.name} fp32_eq64 two-step {nsteps} steps", flush=True)
+    s = solver_for_case(case, "fp32_eq64")
+    s.set_steps_per_pass(2, 16)
+    s.step(nsteps)
+    s.sync()
+    compare(case, s, shock_bubble_centres(n), nsteps, "fp32_eq64")
+    rho2, _, _, T2 = s.moments_device()
+    s.close()
+    one = solver_for_case(case, "fp32_eq64")
+    one.step(nsteps)
+    rho1, _, _, T1 = one.moments_device()
+    d = max(float((rho2 - rho1).abs().max() / rho1.abs().max()),
+            float((T2 - T1).abs().max() / T1.abs().max()))
+    print("two-step vs single-step fields", d, flush=True)
+    assert d < 1e-6, d
+    one.close()
