@@ -6,9 +6,11 @@ One "step" is one time step of the whole hot path (ghosts, moments,
 equilibrium, M / relax / Minv collision, Lax-Wendroff convection, forward
 Euler) over the whole grid of the headline workload: the 4096 x 4096 Mach-5
 shock hitting a dense bubble, FP32 populations with FP64 collision
-(MRT_FP32_EQ64).  value = MLUPS (million lattice-site updates per second),
-populations already resident in HBM.  Extra fields report the FP64 form on
-the same grid, the 1024^2 2D Riemann problem, the batched shock tubes and the
+(MRT_FP32_EQ64), run as the library runs it by default at this size: two
+time steps per kernel pass (32-row bands).  value = MLUPS (million
+lattice-site updates per second), populations already resident in HBM.
+Extra fields report the one-step-per-pass kernel and the FP64 form on the
+same grid, the 1024^2 2D Riemann problem, the batched shock tubes and the
 adjoint step, the roofline of the step kernel, and the oracle's CPU rate on a
 bounded sample.  Prints one JSON line.
 """
@@ -25,22 +27,24 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0               # MI355X HBM3E, published
 BYTES_PER_SITE = {"fp64": 256, "fp32": 128, "fp32_eq64": 128}   # 16 reads + 16 writes
-HEADLINE_TILE_ROWS = 8              # what the tile autotuner picks for this grid
+HEADLINE_PER_PASS = 2               # time steps per kernel pass (the default at this size)
+HEADLINE_BAND_ROWS = 32             # band height of the two-step kernel (the default here)
+HEADLINE_TILE_ROWS = 8              # the one-step kernel's band height for this grid
 
-# HBM traffic of one step_kernel launch on the headline workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, mean over
-# the 6 step dispatches) of
-#   bench.py --steps 5 --warmup 1 --no-cpu --no-extra --copy-calibration
+# HBM traffic of one step2_kernel launch (two steps) on the headline
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE; KiB per
+# dispatch, mean over the step dispatches) of
+#   bench.py --steps 10 --warmup 2 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,315.9 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,315.2 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
-# sources with this digest and this tile height; otherwise the roofline
+# sources with this digest and this band height; otherwise the roofline
 # reports traffic = null.
 MEASURED_TRAFFIC = {
-    "digest": "77008ab351a37d58ee88c9c443c548f99a3a43209ed17768c322adb3078f8a1a",
-    "tile_rows": HEADLINE_TILE_ROWS,
-    "fetch_kib": 683889.6, "fetch_copy_kib": 524315.9,
-    "write_kib": 1048576.2, "write_copy_kib": 1048576.0,
+    "digest": "e250b5a77383c3b7011a05b7bbda42f8f7d6c64865865c9b5bcd99bc31bb1b50",
+    "band_rows": HEADLINE_BAND_ROWS,
+    "fetch_kib": 774133.1, "fetch_copy_kib": 524315.2,
+    "write_kib": 1048576.4, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
@@ -55,13 +59,15 @@ def kernel_digest() -> str:
     with open(os.path.join(csrc, "mrt_kernels.hip")) as fh:
         text = fh.read()
     head = text[:text.index("// ---------------------------------------------------------------- adjoint")]
-    i0 = text.index("hipError_t launch_step(")
-    launcher = text[i0:text.index("\n}\n", i0)]
+    launchers = []
+    for name in ("hipError_t launch_step(", "hipError_t launch_step2("):
+        i0 = text.index(name)
+        launchers.append(text[i0:text.index("\n}\n", i0)])
     with open(os.path.join(csrc, "mrt_api.hip")) as fh:
         api = fh.read()
     layout = api[api.index("// Population layout"):api.index("bool bc_ok(")]
     h = hashlib.sha256()
-    for part in (head, launcher, layout):
+    for part in [head, *launchers, layout]:
         h.update(hashlib.sha256(part.encode()).digest())
     for name in STEP_HEADERS:
         with open(os.path.join(csrc, name), "rb") as fh:
@@ -69,11 +75,13 @@ def kernel_digest() -> str:
     return h.hexdigest()
 
 
-def measured_traffic(precision, tile_rows):
-    """HBM bytes per step-kernel launch (counter readings scaled by the copy
-    calibration), or None when they do not describe the kernel that runs."""
+def measured_traffic(precision, per_pass, band_rows):
+    """HBM bytes per two-step-kernel launch (counter readings scaled by the
+    copy calibration), or None when they do not describe the kernel that
+    runs."""
     m = MEASURED_TRAFFIC
-    if precision != "fp32_eq64" or m["digest"] != kernel_digest() or tile_rows != m["tile_rows"]:
+    if (precision != "fp32_eq64" or per_pass != 2 or m["digest"] != kernel_digest()
+            or band_rows != m["band_rows"]):
         return None
     gib_kib = 1024.0 * 1024.0
     fetch = m["fetch_kib"] * gib_kib / m["fetch_copy_kib"]
@@ -94,14 +102,21 @@ def _events_time(stream, fn, nsteps):
     return e0.elapsed_time(e1) / 1e3
 
 
-def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, scheme=None):
+def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, scheme=None,
+                per_pass=0):
+    """per_pass 1 or 2 with tile_rows: that kernel and band height; else the
+    autotuner's choice (autotune) or the library's default."""
     import torch
 
     from paper_1004_5442_amd.solver import solver_for_case
     s = solver_for_case(case, precision)
     if scheme:
         s.set_scheme(**scheme)
-    if tile_rows:
+    if per_pass == 2:
+        s.set_steps_per_pass(2, tile_rows)
+    elif tile_rows:
+        if precision != "fp64":
+            s.set_steps_per_pass(1, 0)
         s.set_tile(tile_rows)
     elif autotune:
         s.autotune(4)
@@ -111,9 +126,11 @@ def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, sche
     sec = _events_time(torch.cuda.current_stream(), s.step, steps)
     s.sync()      # raises if the run went unhealthy
     tile = s.tile()
+    pp = s.steps_per_pass()
     s.close()
     mlups = case.cells * steps / sec / 1e6
-    return {"mlups": mlups, "sec": sec, "ms_per_step": 1e3 * sec / steps, "tile": tile}
+    return {"mlups": mlups, "sec": sec, "ms_per_step": 1e3 * sec / steps, "tile": tile,
+            "per_pass": pp[0], "band_rows": pp[1]}
 
 
 def time_batch(steps, warmup):
@@ -245,15 +262,23 @@ def time_adjoint(steps):
 
 
 def roofline(case, precision, r, traffic=None):
-    """Algorithmic bytes of one step-kernel launch over the event-timed step
-    (which also holds the ~5 us reflecting-wall ghost launch: achieved is a
-    slight underestimate of the step kernel's own rate)."""
-    per_launch_bytes = BYTES_PER_SITE[precision] * case.cells
-    achieved = per_launch_bytes / (r["sec"] / r["steps"]) / 1e9
-    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "traffic_unit": "bytes per launch", "algorithmic_bytes": per_launch_bytes,
-            "kernel": "step_kernel", "bytes_per_site": BYTES_PER_SITE[precision]}
+    """Algorithmic bytes of one step-kernel launch (bytes per site update x
+    the site updates of one launch: cells x steps per pass) over the
+    event-timed launch (which also holds the ~5 us reflecting-wall ghost
+    launch: achieved is a slight underestimate of the kernel's own rate)."""
+    per_pass = r.get("per_pass", 1)
+    per_launch_bytes = BYTES_PER_SITE[precision] * case.cells * per_pass
+    achieved = per_launch_bytes / (r["sec"] / r["steps"] * per_pass) / 1e9
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "traffic_unit": "bytes per launch", "algorithmic_bytes": per_launch_bytes,
+           "kernel": "step2_kernel" if per_pass == 2 else "step_kernel",
+           "bytes_per_site": BYTES_PER_SITE[precision], "site_updates_per_launch": case.cells * per_pass}
+    if per_pass == 2:
+        out["note"] = ("two time steps per launch: each launch reads f^n once and writes f^{n+2}, so "
+                       "its HBM traffic is about half the per-step algorithmic bytes; the kernel is "
+                       "bound by vector-ALU issue, not HBM")
+    return out
 
 
 def cpu_baseline(rows=512, steps=2):
@@ -286,9 +311,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--tile-rows", type=int, default=HEADLINE_TILE_ROWS,
-                    help="rows per work item of the headline run (0: run the autotuner)")
+    ap.add_argument("--steps-per-pass", type=int, default=HEADLINE_PER_PASS, choices=(1, 2),
+                    help="kernel of the headline run: two time steps per pass or one")
+    ap.add_argument("--rows", type=int, default=0,
+                    help="band height of the headline run (default: 32 for two steps per "
+                         "pass, 8 for one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -311,8 +338,8 @@ def main():
     n = 4096
     head = W.shock_bubble(n=n)
     prec = "fp32_eq64"
-    r = time_solver(head, prec, args.steps, args.warmup, autotune=not args.no_autotune,
-                    tile_rows=args.tile_rows)
+    rows = args.rows or (HEADLINE_BAND_ROWS if args.steps_per_pass == 2 else HEADLINE_TILE_ROWS)
+    r = time_solver(head, prec, args.steps, args.warmup, tile_rows=rows, per_pass=args.steps_per_pass)
     r["steps"] = args.steps
     out = {
         "metric": "MLUPS (million lattice-site updates per second) of the MRT FD-LB step",
@@ -329,27 +356,32 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"shock_bubble {n}x{n} (Mach-5 shock on a density-3 bubble, "
                                f"gamma 1.4, Pr 0.71, reflect/inflow/outflow)",
-                   "cells": head.cells, "precision": prec, "tile_rows": r["tile"][0],
-                   "grid_blocks": r["tile"][1]},
-        "roofline": roofline(head, prec, r, measured_traffic(prec, r["tile"][0])),
+                   "cells": head.cells, "precision": prec, "steps_per_pass": r["per_pass"],
+                   "band_rows": r["band_rows"]},
+        "roofline": roofline(head, prec, r, measured_traffic(prec, r["per_pass"], r["band_rows"])),
     }
     if not args.no_extra:
         extra = {}
         k = max(20, args.steps // 4)
+        k += k & 1
+        r1 = time_solver(head, prec, k, 3, tile_rows=HEADLINE_TILE_ROWS, per_pass=1)
+        r1["steps"] = k
+        extra["fp32_eq64_one_step_per_pass"] = {"mlups": round(r1["mlups"], 1), "band_rows": HEADLINE_TILE_ROWS,
+                                                "roofline_frac": roofline(head, prec, r1)["frac"]}
         r64 = time_solver(head, "fp64", k, 3, tile_rows=HEADLINE_TILE_ROWS)
         r64["steps"] = k
         extra["fp64_same_grid"] = {"mlups": round(r64["mlups"], 1),
                                    "roofline_frac": roofline(head, "fp64", r64)["frac"]}
-        r32 = time_solver(head, "fp32", k, 3, tile_rows=HEADLINE_TILE_ROWS)
+        r32 = time_solver(head, "fp32", k, 3, tile_rows=HEADLINE_BAND_ROWS, per_pass=2)
         r32["steps"] = k
-        extra["fp32_same_grid"] = {"mlups": round(r32["mlups"], 1),
+        extra["fp32_same_grid"] = {"mlups": round(r32["mlups"], 1), "steps_per_pass": 2,
                                    "roofline_frac": roofline(head, "fp32", r32)["frac"]}
         rp = W.riemann2d(n=1024, seed=0)
         for pr in ("fp32_eq64", "fp64"):
             rr = time_solver(rp, pr, 2 * k, 5)
             rr["steps"] = 2 * k
             extra[f"riemann2d_1024_{pr}"] = {
-                "mlups": round(rr["mlups"], 1),
+                "mlups": round(rr["mlups"], 1), "steps_per_pass": rr["per_pass"],
                 "effective_GBs": roofline(rp, pr, rr)["achieved"],
                 "note": "fits the 256 MB Infinity Cache: effective, not HBM, bandwidth"}
         variants = {}
@@ -365,7 +397,7 @@ def main():
             rr["steps"] = 4 * k
             extra[f"rm_instability_360x100_{pr}"] = {
                 "mlups": round(rr["mlups"], 1), "ms_per_step": round(rr["ms_per_step"], 5),
-                "tile_rows": rr["tile"][0],
+                "tile_rows": rr["tile"][0], "steps_per_pass": rr["per_pass"],
                 "note": "36,000 cells: launch-latency bound (captured graphs of 64 steps)"}
         extra["batched_512_tubes"] = time_batch(max(50, args.steps // 2), 5)
         extra["adjoint_256"] = time_adjoint(100)

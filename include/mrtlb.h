@@ -168,12 +168,15 @@ int mrt_sync(mrt_ctx* ctx);
 int mrt_set_tile(mrt_ctx* ctx, int rows_per_item, int grid_blocks);
 int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
 
-/* Time steps per pass over the populations: 1 (default) or 2.  With 2, one
+/* Time steps per pass over the populations: 1 or 2 (default: 2 for FP32
+ * storage grids whose population buffer exceeds the 256 MB last-level cache,
+ * else 1; mrt_autotune times both and keeps the faster).  With 2, one
  * kernel launch advances the state two steps of Eq. 3 (the same per-site
  * arithmetic as two single steps, so the same result up to FP32 rounding
  * order): each work item reads f^n once, keeps f^{n+1} in registers and
  * writes f^{n+2}, recomputing f^{n+1} on the two rows above and below its
- * band of `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = 16) and on its two edge
+ * band of `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = 8 to 32 by grid size)
+ * and on its two edge
  * columns, which halves the memory traffic per step.  An odd last step of
  * mrt_step runs the single-step kernel.  FP32 storage forms and the
  * default scheme only (MRT_EINVAL for MRT_FP64; variants set by
@@ -181,6 +184,7 @@ int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
  * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range, FP64). */
 #define MRT_MAX_BAND_ROWS_2 32
 int mrt_set_steps_per_pass(mrt_ctx* ctx, int steps, int rows);
+int mrt_get_steps_per_pass(const mrt_ctx* ctx, int* steps, int* rows);
 
 /* Scheme variants (the paper's discretisation passage admits three
  * readings; section "Construction", last paragraph before Fig. 1):

@@ -247,8 +247,13 @@ void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
 // go down to one-row bands so that they still spread over the chip.
 // Default band height of the two-step kernel: each band recomputes f^{n+1}
 // on two extra rows, so taller bands waste less (1/rows) but give fewer
-// blocks.
-constexpr int kDefaultRows2 = 16;
+// blocks: up to 32 rows while the grid still gives ~2048 work items (four
+// per block slot of the chip at two blocks per CU), at least 8.
+int default_rows2(int nx, int ny) {
+    const long long chunks = (nx + 255) / 256;
+    const long long r = std::max<long long>(8, std::min<long long>(32, chunks * ny / 2048));
+    return int(std::min<long long>(r, ny));
+}
 
 int default_rows(int nx, int ny) {
     const long long chunks = (nx + 255) / 256;
@@ -452,6 +457,12 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     if (build_adjoint_items(c) != MRT_OK) return fail(MRT_EDEVICE);
     c->nt = (long long)bytes > kNonTemporalBytes;
     c->walls = has_kind(bc, MRT_BC_REFLECT) && (long long)nx * ny <= kWallsInKernelCells;
+    // FP32 storage grids larger than the last-level cache (HBM-bound with
+    // one step per pass) run two steps per pass by default
+    if (precision != MRT_FP64 && c->nt) {
+        if (build_items2(c, default_rows2(nx, ny)) != MRT_OK) return fail(MRT_EDEVICE);
+        c->per_pass = 2;
+    }
     (void)ctx_err;
     *out = c;
     return MRT_OK;
@@ -692,7 +703,7 @@ int mrt_set_steps_per_pass(mrt_ctx* c, int steps, int rows) {
     if (steps == 2 && c->prec == MRT_FP64)
         return ctx_fail(c, MRT_EINVAL, "two steps per pass need FP32 storage");
     if (steps == 2) {
-        const int r = std::min(rows > 0 ? rows : kDefaultRows2, c->ny);
+        const int r = std::min(rows > 0 ? rows : default_rows2(c->nx, c->ny), c->ny);
         if (r != c->rows2 || !c->d_items2) {
             const int rc = build_items2(c, r);
             if (rc != MRT_OK) return rc;
@@ -733,6 +744,13 @@ int mrt_set_scheme(mrt_ctx* c, int flags) {
     return MRT_OK;
 }
 
+int mrt_get_steps_per_pass(const mrt_ctx* c, int* steps, int* rows) {
+    if (!c) return MRT_EINVAL;
+    if (steps) *steps = c->per_pass;
+    if (rows) *rows = c->per_pass == 2 ? c->rows2 : c->rows;
+    return MRT_OK;
+}
+
 int mrt_get_tile(const mrt_ctx* c, int* rows, int* grid) {
     if (!c) return MRT_EINVAL;
     if (rows) *rows = c->rows;
@@ -757,6 +775,7 @@ int mrt_autotune(mrt_ctx* c, int steps) {
     HIPTRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int row_opts[] = {1, 2, 3, 4, 5, 6, 8, 12, 16, 32, 64, 128};
     const int grid_mult[] = {0, 2, 4, 8};
+    c->per_pass = 1;
     float best = 1e30f;
     int best_rows = c->rows, best_grid = c->grid;
     for (int r : row_opts) {
@@ -784,6 +803,33 @@ int mrt_autotune(mrt_ctx* c, int steps) {
             HIPTRY(hipMemcpyAsync(c->f[c->cur], save, bytes, hipMemcpyDeviceToDevice, c->stream));
         }
     }
+    // two steps per pass (FP32 storage), per step
+    int best_pass = 1, best_rows2 = 0;
+    if (c->prec != MRT_FP64) {
+        best /= float(steps);
+        const int steps2 = steps + (steps & 1);
+        const int rows2_opts[] = {8, 16, 32};
+        for (int r : rows2_opts) {
+            if (r > c->ny && r != rows2_opts[0]) break;
+            if (build_items2(c, std::min(r, c->ny)) != MRT_OK) return MRT_EDEVICE;
+            c->per_pass = 2;
+            c->eager = true;
+            mrt_step(c, 2);
+            HIPTRY(hipEventRecord(e0, c->stream));
+            mrt_step(c, steps2);
+            HIPTRY(hipEventRecord(e1, c->stream));
+            c->eager = false;
+            HIPTRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / float(steps2) < best) {
+                best = ms / float(steps2);
+                best_pass = 2;
+                best_rows2 = c->rows2;
+            }
+            HIPTRY(hipMemcpyAsync(c->f[c->cur], save, bytes, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
     HIPTRY(hipStreamSynchronize(c->stream));
     HIPTRY(hipEventDestroy(e0));
     HIPTRY(hipEventDestroy(e1));
@@ -791,6 +837,10 @@ int mrt_autotune(mrt_ctx* c, int steps) {
     HIPTRY(hipMemsetAsync(c->d_health, 0, sizeof(unsigned), c->stream));
     if (build_items(c, best_rows) != MRT_OK) return MRT_EDEVICE;
     c->grid = best_grid;
+    c->per_pass = best_pass;
+    if (best_pass == 2 && build_items2(c, best_rows2) != MRT_OK) return MRT_EDEVICE;
+    c->graphs.clear();
+    c->graphs2.clear();
     HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
 }

@@ -66,6 +66,7 @@ _proto = {
     "mrt_get_tile": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int)]),
     "mrt_set_scheme": (c_int, [c_void_p, c_int]),
     "mrt_set_steps_per_pass": (c_int, [c_void_p, c_int, c_int]),
+    "mrt_get_steps_per_pass": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int)]),
     "mrt_autotune": (c_int, [c_void_p, c_int]),
     "mrt_destroy": (None, [c_void_p]),
     "mrt_last_error": (ctypes.c_char_p, [c_void_p]),

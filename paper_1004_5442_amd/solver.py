@@ -151,6 +151,12 @@ class Solver:
         band height of the two-step kernel (0: default)."""
         self._check(L.raw().mrt_set_steps_per_pass(self._h, int(steps), int(rows)))
 
+    def steps_per_pass(self):
+        """(steps per pass, band rows of the kernel that runs)"""
+        k, r = c_int(), c_int()
+        self._check(L.raw().mrt_get_steps_per_pass(self._h, byref(k), byref(r)))
+        return k.value, r.value
+
     def set_tile(self, rows: int, grid: int = 0):
         self._check(L.raw().mrt_set_tile(self._h, int(rows), int(grid)))
 

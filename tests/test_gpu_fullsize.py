@@ -1,7 +1,9 @@
 """GPU parity at full size, in the launch configuration the benchmark times.
 
 The 4096^2 shock-bubble grid (FP32 storage: 1.15 GB per population buffer,
-so the step kernel takes its non-temporal store path) and the 1024^2 2D
+so the kernels take their non-temporal store path, and FP32 storage runs two
+steps per pass by default; the one-step kernel is checked there too) and
+the 1024^2 2D
 Riemann grid (cache-resident, cached stores) run a few steps on the GPU; the
 oracle evaluates small windows around sampled cells (the shock front, the
 bubble edge, every kind of boundary, the corners) one by one
@@ -25,7 +27,8 @@ if not torch.cuda.is_available():
 
 from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
 
-HEADLINE_TILE_ROWS = 8       # the tile the benchmark runs the 4096^2 grid with
+HEADLINE_BAND_ROWS_2 = 32    # the benchmark's 4096^2 FP32 run: two steps per pass, 32-row bands
+HEADLINE_TILE_ROWS = 8       # its one-step-per-pass runs (FP64, and FP32 for comparison)
 NSTEPS = 6                   # steps before sampling (window margin = NSTEPS)
 PATCH = 6                    # sampled patch: PATCH x PATCH cells
 
@@ -99,13 +102,20 @@ def shock_bubble_centres(n):
             (0, 0), (n - 1, n - 1), (0, n - 1), (n - 1, 0)]   # corners
 
 
-@pytest.mark.parametrize("precision", ["fp32_eq64", "fp64"])
-def test_shock_bubble_4096_sampled(precision):
+@pytest.mark.parametrize("precision,per_pass,rows", [("fp32_eq64", 2, HEADLINE_BAND_ROWS_2),
+                                                     ("fp32_eq64", 1, HEADLINE_TILE_ROWS),
+                                                     ("fp64", 1, HEADLINE_TILE_ROWS)])
+def test_shock_bubble_4096_sampled(precision, per_pass, rows):
     n = 4096
     case = W.shock_bubble(n=n)
-    print(f"case {case.name} {precision} tile {HEADLINE_TILE_ROWS}", flush=True)
+    print(f"case {case.name} {precision} {per_pass} steps per pass, {rows}-row bands", flush=True)
     s = solver_for_case(case, precision)
-    s.set_tile(HEADLINE_TILE_ROWS)
+    if per_pass == 2:
+        s.set_steps_per_pass(2, rows)
+    else:
+        if precision != "fp64":
+            s.set_steps_per_pass(1, 0)
+        s.set_tile(rows)
     s.step(NSTEPS)
     s.sync()
     compare(case, s, shock_bubble_centres(n), NSTEPS, precision)
@@ -151,7 +161,10 @@ def test_shock_bubble_4096_mirror_symmetry(precision):
     case = W.shock_bubble(n=n)
     print(f"case {case.name} {precision} {steps} steps symmetry, tol {tol}", flush=True)
     s = solver_for_case(case, precision)
-    s.set_tile(HEADLINE_TILE_ROWS)
+    if precision == "fp64":
+        s.set_tile(HEADLINE_TILE_ROWS)
+    else:
+        s.set_steps_per_pass(2, HEADLINE_BAND_ROWS_2)
     s.step(steps)
     rho, ux, uy, T = s.moments_device()
     s.sync()
@@ -167,17 +180,22 @@ def test_shock_bubble_4096_mirror_symmetry(precision):
     assert float(rho[n // 2, int(0.1 * n) + 10]) > 1.5
 
 
-def test_largest_grids_use_the_full_32_bit_offset_range():
+@pytest.mark.parametrize("per_pass", [2, 1])
+def test_largest_grids_use_the_full_32_bit_offset_range(per_pass):
     """12000 x 12000 cells, FP32 storage: 2.36e9 elements per state, past
-    the 2^31 that signed 32-bit row offsets would reach.  A few steps, then
-    patches at the shock, the bubble, the walls and the corners against the
-    oracle."""
+    the 2^31 that signed 32-bit row offsets would reach, with the two-step
+    kernel (the default at this size) and the one-step kernel.  A few
+    steps, then patches at the shock, the bubble, the walls and the corners
+    against the oracle."""
     n = 12000
     case = W.shock_bubble(n=n)
-    print(f"case {case.name} fp32_eq64 {NSTEPS} steps", flush=True)
+    print(f"case {case.name} fp32_eq64 {NSTEPS} steps, {per_pass} per pass", flush=True)
     s = solver_for_case(case, "fp32_eq64")
     assert s.population_bytes() > 4 * 2 ** 31
-    s.set_tile(HEADLINE_TILE_ROWS)
+    assert s.steps_per_pass()[0] == 2
+    if per_pass == 1:
+        s.set_steps_per_pass(1, 0)
+        s.set_tile(HEADLINE_TILE_ROWS)
     s.step(NSTEPS)
     s.sync()
     centres = [(int(0.1 * n), n // 2), (int(0.1 * n), 0), (int(0.15 * n), n // 2),
@@ -186,11 +204,14 @@ def test_largest_grids_use_the_full_32_bit_offset_range():
     s.close()
 
 
-def test_large_grid_with_reflecting_walls_on_every_side():
+@pytest.mark.parametrize("precision", ["fp64", "fp32_eq64"])
+def test_large_grid_with_reflecting_walls_on_every_side(precision):
     """Above 2^22 cells the reflecting-wall ghosts come from the separate
     ghost pass (smaller grids write them in the step kernel): a 2048 x 2049
-    2D Riemann grid with reflecting walls on all four sides, sampled at the
-    walls, the corners and the quadrant interfaces after a few steps."""
+    2D Riemann grid (FP32: 304 MB per state, so two steps per pass; an odd
+    step count, so the last step is a one-step pass) with reflecting walls
+    on all four sides, sampled at the walls, the corners and the quadrant
+    interfaces after a few steps."""
     import dataclasses
     base = W.riemann2d(n=2048, seed=4)
     rows = 2049
@@ -199,14 +220,16 @@ def test_large_grid_with_reflecting_walls_on_every_side():
                                ux=pad(base.ux), uy=pad(base.uy), T=pad(base.T),
                                bc=("reflect",) * 4)
     assert case.cells > 1 << 22
-    print(f"case {case.name} fp64 ghost pass", flush=True)
-    s = solver_for_case(case, "fp64")
+    print(f"case {case.name} {precision} ghost pass", flush=True)
+    s = solver_for_case(case, precision)
     s.set_tile(HEADLINE_TILE_ROWS)
-    s.step(NSTEPS)
+    if precision != "fp64":
+        assert s.steps_per_pass()[0] == 2
+    s.step(NSTEPS + 1)
     s.sync()
     nx, ny = case.nx, case.ny
     centres = [(0, ny // 3), (nx - 1, 2 * ny // 3), (nx // 3, 0), (2 * nx // 3, ny - 1),
                (0, 0), (nx - 1, 0), (0, ny - 1), (nx - 1, ny - 1), (nx // 2, ny // 2),
                (nx // 2, 0), (0, ny // 2)]
-    compare(case, s, centres, NSTEPS, "fp64")
+    compare(case, s, centres, NSTEPS + 1, precision)
     s.close()

@@ -52,6 +52,7 @@ def test_two_step_matches_oracle_and_single_step(bc, shape, rows):
     print(f"case {case.name} bc={bc} rows={rows} fp32_eq64 two-step", flush=True)
     want, p = oracle_run(case, nsteps)
     one = solver_for_case(case, "fp32_eq64")
+    one.set_steps_per_pass(1, 0)
     one.step(nsteps)
     two = solver_for_case(case, "fp32_eq64")
     two.set_steps_per_pass(2, rows)
@@ -134,6 +135,25 @@ def test_rejected_settings():
     s.close()
 
 
+def test_default_and_autotuned_path():
+    """Cache-resident grids default to one step per pass; the autotuner
+    times both paths and keeps either, and the state is unchanged by it."""
+    case = smooth_case(300, 40, ("reflect", "eq", "periodic", "periodic"), seed=9)
+    s = solver_for_case(case, "fp32_eq64")
+    assert s.steps_per_pass()[0] == 1
+    before = s.populations()
+    s.autotune(4)
+    assert np.array_equal(s.populations(), before)
+    k, rows = s.steps_per_pass()
+    print("autotuned", k, rows, s.tile(), flush=True)
+    assert k in (1, 2) and rows >= 1
+    want, p = oracle_run(case, 9)
+    s.step(9)
+    err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+    assert max(err.values()) < 1e-5, err
+    s.close()
+
+
 def test_variants_run_one_step_per_pass():
     """A scheme variant ignores the two-step setting (its own kernels)."""
     case = smooth_case(150, 37, ("eq", "outflow", "reflect", "reflect"), seed=2)
@@ -148,7 +168,8 @@ def test_variants_run_one_step_per_pass():
 
 
 def test_shock_bubble_4096_two_step_sampled():
-    """The benchmark grid (FP32 storage, non-temporal stores, 16-row bands):
+    """The benchmark grid (FP32 storage, non-temporal stores; 16-row bands here,
+    the default 32 in the sampled test of the full-size module):
     7 steps (three passes and a single step), then patches at the shock, the
     bubble, the walls, inflow, outflow and the corners against the oracle's
     windowed evaluation, and the whole state against the single-step path."""
@@ -157,13 +178,17 @@ def test_shock_bubble_4096_two_step_sampled():
     case = W.shock_bubble(n=n)
     print(f"case {case.name} fp32_eq64 two-step {nsteps} steps", flush=True)
     s = solver_for_case(case, "fp32_eq64")
+    assert s.steps_per_pass() == (2, 32)        # the default at this size
     s.set_steps_per_pass(2, 16)
+    assert s.steps_per_pass() == (2, 16)
     s.step(nsteps)
     s.sync()
     compare(case, s, shock_bubble_centres(n), nsteps, "fp32_eq64")
     rho2, _, _, T2 = s.moments_device()
     s.close()
     one = solver_for_case(case, "fp32_eq64")
+    one.set_steps_per_pass(1, 0)
+    one.set_tile(8)
     one.step(nsteps)
     rho1, _, _, T1 = one.moments_device()
     d = max(float((rho2 - rho1).abs().max() / rho1.abs().max()),
