@@ -308,12 +308,18 @@ int mrt_batch_prepare_steps(mrt_batch* b, int n);
 int mrt_batch_read_moments(mrt_batch* b, int i, double* rho, double* ux, double* uy, double* T);
 /* Unpadded FP64 populations of instance i (16*ny*nx host doubles). */
 int mrt_batch_get_populations(mrt_batch* b, int i, double* f);
-/* Rows per work item (each work item is 64 columns wide) and workgroups
- * launched (0 = one wave per work item); autotune times candidates on the
- * current state (saved and restored) and keeps the fastest.  Changing the
- * tile drops the captured graphs. */
+/* Rows per work item of the one-step kernel (each work item is 256 columns
+ * of one instance, one 4-wave workgroup) and workgroups launched (0 = one
+ * per work item); autotune times candidates, one and two steps per pass, on
+ * the current state (saved and restored) and keeps the fastest.  Changing
+ * the tile drops the captured graphs. */
 int mrt_batch_set_tile(mrt_batch* b, int rows_per_item, int grid_blocks);
 int mrt_batch_get_tile(const mrt_batch* b, int* rows_per_item, int* grid_blocks);
+/* As mrt_set_steps_per_pass, for every instance of the batch (default 1;
+ * rows 0 = 32, bands never exceed an instance's height).  Synchronises.
+ * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range, FP64). */
+int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows);
+int mrt_batch_get_steps_per_pass(const mrt_batch* b, int* steps, int* rows);
 int mrt_batch_autotune(mrt_batch* b, int steps_per_trial);
 long long mrt_batch_cells(const mrt_batch* b);
 void mrt_batch_destroy(mrt_batch* b);

@@ -72,6 +72,15 @@ class Batch:
         self._check(L.raw().mrt_batch_get_tile(self._h, byref(r), byref(g)))
         return r.value, g.value
 
+    def set_steps_per_pass(self, steps: int, rows: int = 0):
+        """1 or 2 time steps per kernel pass (mrt_batch_set_steps_per_pass)."""
+        self._check(L.raw().mrt_batch_set_steps_per_pass(self._h, int(steps), int(rows)))
+
+    def steps_per_pass(self):
+        k, r = c_int(), c_int()
+        self._check(L.raw().mrt_batch_get_steps_per_pass(self._h, byref(k), byref(r)))
+        return k.value, r.value
+
     def autotune(self, steps: int = 8):
         self._check(L.raw().mrt_batch_autotune(self._h, int(steps)))
         return self.tile()

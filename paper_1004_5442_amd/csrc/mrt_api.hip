@@ -1018,6 +1018,10 @@ struct mrt_batch {
     double* d_stage = nullptr;
     unsigned* d_health = nullptr;
     GraphCache graphs;                      // captured steps
+    int per_pass = 1;                       // time steps per pass (1 or 2)
+    Item* d_items2 = nullptr;               // work items of the two-step kernel
+    int nitems2 = 0, rows2 = 0;
+    GraphCache graphs2;                     // captured two-step passes
     std::string err;
 };
 
@@ -1037,6 +1041,23 @@ int batch_items(mrt_batch* b, int rows) {
     b->nitems = int(items.size());
     b->rows = rows;
     b->graphs.clear();
+    return MRT_OK;
+}
+
+// Work items of the two-step kernel: bands of at most `rows` <= 32 rows per
+// instance (the instance table is not touched).
+int batch_items2(mrt_batch* b, int rows) {
+    std::string& ctx_err = b->err;
+    std::vector<Item> items;
+    for (int i = 0; i < b->count; ++i)
+        add_items(items, i, b->insts[i].nx, b->insts[i].ny, std::min(rows, b->insts[i].ny));
+    if (b->d_items2) HIPTRY(hipFree(b->d_items2));
+    b->d_items2 = nullptr;
+    HIPTRY(hipMalloc(&b->d_items2, items.size() * sizeof(Item)));
+    HIPTRY(hipMemcpy(b->d_items2, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    b->nitems2 = int(items.size());
+    b->rows2 = rows;
+    b->graphs2.clear();
     return MRT_OK;
 }
 
@@ -1146,6 +1167,29 @@ static int batch_step_impl(mrt_batch* b, int n, bool launch) {
     if (!b || n < 0) return MRT_EINVAL;
     std::string& ctx_err = b->err;
     if (n == 0) return MRT_OK;
+    if (b->per_pass == 2) {
+        // two steps per pass, an odd last step by the single-step kernel;
+        // the reflecting-wall ghosts are refilled before every launch
+        auto ghosts = [&](int cur, hipStream_t st) -> hipError_t {
+            return b->any_reflect ? mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[cur], 1, st)
+                                  : hipSuccess;
+        };
+        auto enqueue2 = [&](int cur, hipStream_t st) -> hipError_t {
+            const hipError_t e = ghosts(cur, st);
+            if (e != hipSuccess) return e;
+            return mrt::k_step2(b->prec, b->d_insts, b->d_items2, b->nitems2, b->f[cur], b->f[1 - cur],
+                                b->d_health, 0, b->nt, st);
+        };
+        const int pairs = n / 2;
+        if (pairs > 0) HIPTRY(run_graphs(b->graphs2, b->cur, pairs, b->stream, enqueue2, launch));
+        if ((n & 1) && launch) {
+            HIPTRY(ghosts(b->cur, b->stream));
+            HIPTRY(mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[b->cur], b->f[1 - b->cur],
+                               b->d_health, b->grid, b->nt, false, b->stream));
+            b->cur ^= 1;
+        }
+        return MRT_OK;
+    }
     // reflecting-wall ghosts: written by the step kernel with its output
     // (b->walls), else refilled before each step
     auto enqueue = [&](int cur, hipStream_t st) -> hipError_t {
@@ -1206,6 +1250,37 @@ int mrt_batch_set_tile(mrt_batch* b, int rows, int grid) {
     return MRT_OK;
 }
 
+int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows) {
+    if (!b) return MRT_EINVAL;
+    std::string& ctx_err = b->err;
+    if (steps != 1 && steps != 2) return (b->err = "steps per pass: 1 or 2", MRT_EINVAL);
+    if (rows < 0 || rows > MRT_MAX_BAND_ROWS_2) return (b->err = "rows: 0 (default) to 32", MRT_EINVAL);
+    if (steps == 2 && b->prec == MRT_FP64) return (b->err = "two steps per pass need FP32 storage", MRT_EINVAL);
+    if (steps == 2) {
+        const int r = rows > 0 ? rows : MRT_MAX_BAND_ROWS_2;
+        if (r != b->rows2 || !b->d_items2) {
+            const int rc = batch_items2(b, r);
+            if (rc != MRT_OK) return rc;
+        }
+    }
+    b->per_pass = steps;
+    b->graphs.clear();
+    b->graphs2.clear();
+    // the two-step path leaves the reflecting ghosts of the current state
+    // stale; the single-step kernel with in-kernel walls expects them current
+    if (b->any_reflect)
+        HIPTRY(mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[b->cur], 1, b->stream));
+    HIPTRY(hipStreamSynchronize(b->stream));
+    return MRT_OK;
+}
+
+int mrt_batch_get_steps_per_pass(const mrt_batch* b, int* steps, int* rows) {
+    if (!b) return MRT_EINVAL;
+    if (steps) *steps = b->per_pass;
+    if (rows) *rows = b->per_pass == 2 ? b->rows2 : b->rows;
+    return MRT_OK;
+}
+
 int mrt_batch_get_tile(const mrt_batch* b, int* rows, int* grid) {
     if (!b) return MRT_EINVAL;
     if (rows) *rows = b->rows;
@@ -1234,6 +1309,7 @@ int mrt_batch_autotune(mrt_batch* b, int steps) {
     float best = 1e30f;
     int best_rows = b->rows, best_grid = b->grid;
     const int cur0 = b->cur;
+    b->per_pass = 1;
     for (int r : row_opts) {
         if (r > maxny) break;
         for (int gm : grid_mult) {
@@ -1255,12 +1331,40 @@ int mrt_batch_autotune(mrt_batch* b, int steps) {
             HIPTRY(hipMemcpyAsync(b->f[b->cur], save, bytes, hipMemcpyDeviceToDevice, b->stream));
         }
     }
+    // two steps per pass (FP32 storage), per step
+    int best_pass = 1, best_rows2 = 0;
+    if (b->prec != MRT_FP64) {
+        best /= float(steps);
+        const int steps2 = steps + (steps & 1);
+        const int rows2_opts[] = {4, 8, 16, 32};
+        for (int r : rows2_opts) {
+            if (r > maxny && r != rows2_opts[0]) break;
+            if (batch_items2(b, r) != MRT_OK) return MRT_EDEVICE;
+            b->per_pass = 2;
+            mrt_batch_step(b, steps2);    // capture + warm-up
+            HIPTRY(hipEventRecord(e0, b->stream));
+            mrt_batch_step(b, steps2);
+            HIPTRY(hipEventRecord(e1, b->stream));
+            HIPTRY(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms / float(steps2) < best) {
+                best = ms / float(steps2);
+                best_pass = 2;
+                best_rows2 = r;
+            }
+            b->cur = cur0;
+            HIPTRY(hipMemcpyAsync(b->f[b->cur], save, bytes, hipMemcpyDeviceToDevice, b->stream));
+        }
+    }
     HIPTRY(hipStreamSynchronize(b->stream));
     HIPTRY(hipEventDestroy(e0));
     HIPTRY(hipEventDestroy(e1));
     HIPTRY(hipFree(save));
     HIPTRY(hipMemsetAsync(b->d_health, 0, sizeof(unsigned), b->stream));
-    const int rc = mrt_batch_set_tile(b, best_rows, best_grid);
+    b->per_pass = 1;
+    int rc = mrt_batch_set_tile(b, best_rows, best_grid);
+    if (rc == MRT_OK && best_pass == 2) rc = mrt_batch_set_steps_per_pass(b, 2, best_rows2);
     HIPTRY(hipStreamSynchronize(b->stream));
     return rc;
 }
@@ -1271,6 +1375,8 @@ void mrt_batch_destroy(mrt_batch* b) {
     if (!b) return;
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     b->graphs.clear();
+    b->graphs2.clear();
+    if (b->d_items2) (void)hipFree(b->d_items2);
     if (b->f[0]) (void)hipFree(b->f[0]);
     if (b->f[1]) (void)hipFree(b->f[1]);
     if (b->d_insts) (void)hipFree(b->d_insts);

@@ -87,6 +87,8 @@ _proto = {
     "mrt_batch_get_populations": (c_int, [c_void_p, c_int, c_void_p]),
     "mrt_batch_set_tile": (c_int, [c_void_p, c_int, c_int]),
     "mrt_batch_get_tile": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int)]),
+    "mrt_batch_set_steps_per_pass": (c_int, [c_void_p, c_int, c_int]),
+    "mrt_batch_get_steps_per_pass": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int)]),
     "mrt_batch_autotune": (c_int, [c_void_p, c_int]),
     "mrt_batch_cells": (c_longlong, [c_void_p]),
     "mrt_batch_destroy": (None, [c_void_p]),

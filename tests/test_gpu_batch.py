@@ -53,6 +53,32 @@ def test_tube_batch_fp32_matches_oracle(precision):
         assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
 
 
+@pytest.mark.parametrize("rows", [4, 32])
+def test_two_step_batch_matches_oracle_and_single_step(rows):
+    """Two steps per pass over the mixed batch (ragged sizes, every
+    boundary kind, a one-column and a one-row instance, gamma 5/3 and
+    tubes), 13 steps per call (six passes and a one-step pass) over three
+    calls, against the oracle and the one-step batch."""
+    cases = _mixed_cases()
+    one = Batch(cases, "fp32_eq64")
+    two = Batch(cases, "fp32_eq64")
+    two.set_steps_per_pass(2, rows)
+    assert two.steps_per_pass() == (2, rows)
+    for call in range(3):
+        print(f"call {call} rows {rows}", flush=True)
+        one.step(13)
+        two.step(13)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 39)
+        err = field_errors(two.moments(i), mrt.macroscopic(want, p.b))
+        tol = fp32_tolerances(c, 39, want)
+        a, b = two.populations(i), one.populations(i)
+        d = float(np.max(np.abs(a - b)) / np.abs(b).max())
+        print(c.name, err, "vs one step", d, flush=True)
+        assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+        assert d < 1e-6, (c.name, d)
+
+
 def test_full_batch_512_tubes_sampled():
     """The full batched workload (512 tubes, 1000 steps, FP32 + FP64
     collision) in its autotuned launch; the three shortest tubes are
@@ -60,6 +86,7 @@ def test_full_batch_512_tubes_sampled():
     cases = W.tube_batch(512, seed=0)
     b = Batch(cases, "fp32_eq64")
     b.autotune(4)
+    print("autotuned", b.tile(), b.steps_per_pass(), flush=True)
     b.step(1000)
     order = np.argsort([c.nx for c in cases])[:3]
     for i in order:
