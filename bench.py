@@ -36,15 +36,15 @@ HEADLINE_TILE_ROWS = 8              # the one-step kernel's band height for this
 # dispatch, mean over the step dispatches) of
 #   bench.py --steps 10 --warmup 2 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,315.2 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,316.1 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this band height; otherwise the roofline
 # reports traffic = null.
 MEASURED_TRAFFIC = {
-    "digest": "e250b5a77383c3b7011a05b7bbda42f8f7d6c64865865c9b5bcd99bc31bb1b50",
+    "digest": "28dc367b7c3ca530f36fb956aedfb5dfb12e996e8d6179a581f8972afb181e4d",
     "band_rows": HEADLINE_BAND_ROWS,
-    "fetch_kib": 774133.1, "fetch_copy_kib": 524315.2,
-    "write_kib": 1048576.4, "write_copy_kib": 1048576.0,
+    "fetch_kib": 770469.5, "fetch_copy_kib": 524316.1,
+    "write_kib": 1048576.3, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
@@ -150,9 +150,11 @@ def time_batch(steps, warmup):
     b.moments(0)              # raises if any instance went unhealthy
     cells = b.cells
     tile = b.tile()
+    pp = b.steps_per_pass()
     b.close()
     return {"mlups": round(cells * steps / sec / 1e6, 1), "cells": cells, "instances": len(cases),
             "ms_per_step": round(1e3 * sec / steps, 4), "tile_rows": tile[0],
+            "steps_per_pass": pp[0], "band_rows": pp[1],
             "roofline_frac": round(cells * 128 * steps / sec / 1e9 / HBM_PEAK_GBS, 4)}
 
 
