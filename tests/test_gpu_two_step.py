@@ -196,3 +196,50 @@ def test_shock_bubble_4096_two_step_sampled():
     print("two-step vs single-step fields", d, flush=True)
     assert d < 1e-6, d
     one.close()
+
+
+def population_totals(solver):
+    """Sum over the grid of each population of the current state, in FP64 on
+    the device, read from the padded layout (16 values)."""
+    cur, _ = solver.buffers()
+    buf = next(b for b in solver._bufs if b.data_ptr() == cur)
+    flat = buf.view(solver.storage_dtype)
+    v = torch.as_strided(flat, size=(solver.ny, 16, solver.nx),
+                         stride=(solver.pitch, solver.plane, 1), storage_offset=solver.origin)
+    return v.double().sum(dim=(0, 2)).cpu().numpy()
+
+
+def test_two_step_conserves_mass_momentum_energy_at_full_size():
+    """A property that holds at any size: on a periodic grid the scheme
+    conserves total mass, momentum and energy (the collision conserves them
+    per cell, the Lax-Wendroff increments telescope).  2048^2 cells (304 MB
+    per FP32 state: two steps per pass by default), 1000 steps: the totals
+    may move only by FP32 rounding.  Then bitwise determinism of the pass."""
+    n, steps = 2048, 1000
+    case = smooth_case(n, n, ("periodic",) * 4, seed=13, amp=0.05)
+    print(f"case {case.name} fp32_eq64 {steps} steps conservation", flush=True)
+    s = solver_for_case(case, "fp32_eq64")
+    assert s.steps_per_pass()[0] == 2
+    vx, vy, eta = mrt.velocity_set(2.5)
+    weights = np.stack([np.ones(16), vx, vy, vx * vx + vy * vy + eta * eta])
+    before = weights @ population_totals(s)
+    s.step(steps)
+    s.sync()
+    after = weights @ population_totals(s)
+    mass, energy = before[0], before[3]
+    drift = {"mass": abs(after[0] - mass) / mass,
+             "momentum": float(np.max(np.abs(after[1:3] - before[1:3]))) / mass,
+             "energy": abs(after[3] - energy) / energy}
+    print("drift", drift, flush=True)
+    assert all(v < 1e-6 for v in drift.values()), drift
+    s.close()
+    outs = []
+    for _ in range(2):
+        r = solver_for_case(case, "fp32_eq64")
+        r.step(50)
+        cur, _ = r.buffers()
+        flat = next(b for b in r._bufs if b.data_ptr() == cur).view(r.storage_dtype)
+        outs.append(torch.as_strided(flat, size=(r.ny, 16, r.nx), stride=(r.pitch, r.plane, 1),
+                                     storage_offset=r.origin).clone())
+        r.close()
+    assert torch.equal(outs[0], outs[1])
