@@ -763,6 +763,12 @@ int mrt_autotune(mrt_ctx* c, int steps) {
     std::string& ctx_err = c->err;
     if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
     if (steps < 1) steps = 4;
+    // the saved state must carry current reflecting-wall ghosts (after
+    // two-step passes they are stale), whichever kernel is chosen
+    {
+        const int rc = fill_ghosts(c);
+        if (rc != MRT_OK) return rc;
+    }
     const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));
     void* save = nullptr;
     HIPTRY(hipMalloc(&save, bytes));
@@ -1292,6 +1298,10 @@ int mrt_batch_autotune(mrt_batch* b, int steps) {
     if (!b) return MRT_EINVAL;
     std::string& ctx_err = b->err;
     if (steps < 1) steps = 8;
+    // the saved state must carry current reflecting-wall ghosts (after
+    // two-step passes they are stale), whichever kernel is chosen
+    if (b->any_reflect)
+        HIPTRY(mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[b->cur], 1, b->stream));
     const size_t bytes = size_t(b->total_elems) * elem_size(b->prec);
     void* save = nullptr;
     HIPTRY(hipMalloc(&save, bytes));

@@ -79,6 +79,23 @@ def test_two_step_batch_matches_oracle_and_single_step(rows):
         assert d < 1e-6, (c.name, d)
 
 
+def test_batch_autotune_after_two_step_passes():
+    """As for a single grid: the batch autotuner refreshes the reflecting
+    ghosts that two-step passes left stale before it times and restores."""
+    cases = _mixed_cases()
+    b = Batch(cases, "fp32_eq64")
+    b.set_steps_per_pass(2, 8)
+    b.step(10)
+    b.autotune(4)
+    print("autotuned", b.tile(), b.steps_per_pass(), flush=True)
+    b.step(9)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 19)
+        err = field_errors(b.moments(i), mrt.macroscopic(want, p.b))
+        tol = fp32_tolerances(c, 19, want)
+        assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+
+
 def test_full_batch_512_tubes_sampled():
     """The full batched workload (512 tubes, 1000 steps, FP32 + FP64
     collision) in its autotuned launch; the three shortest tubes are

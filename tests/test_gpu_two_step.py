@@ -154,6 +154,25 @@ def test_default_and_autotuned_path():
     s.close()
 
 
+@pytest.mark.parametrize("bc", [("reflect", "reflect", "reflect", "reflect"),
+                                ("eq", "outflow", "reflect", "reflect")])
+def test_autotune_after_two_step_passes(bc):
+    """Two-step passes leave the reflecting-wall ghosts of the current
+    state stale; the autotuner (which may then choose the one-step kernel,
+    whose small-grid form trusts those ghosts) refreshes them first."""
+    case = smooth_case(300, 40, bc, seed=17)
+    s = solver_for_case(case, "fp32_eq64")
+    s.set_steps_per_pass(2, 8)
+    s.step(10)
+    s.autotune(4)
+    print("autotuned", s.steps_per_pass(), s.tile(), flush=True)
+    s.step(9)
+    want, p = oracle_run(case, 19)
+    err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+    assert max(err.values()) < 1e-5, err
+    s.close()
+
+
 def test_variants_run_one_step_per_pass():
     """A scheme variant ignores the two-step setting (its own kernels)."""
     case = smooth_case(150, 37, ("eq", "outflow", "reflect", "reflect"), seed=2)
