@@ -127,17 +127,22 @@ int mrt_set_fields(mrt_ctx* ctx, const double* rho, const double* ux, const doub
                    const double* T, int on_device);
 
 /* Advance n time steps (Eq. 3, forward Euler, Lax-Wendroff).  Asynchronous.
- * Health (NaN, rho <= 0, T <= 0) is recorded on the device and reported by
- * the next synchronising call.  Errors: MRT_ESTATE, MRT_EINVAL (n < 0). */
+ * One kernel pass per step, or per two steps (mrt_set_steps_per_pass; the
+ * default for FP32 storage grids larger than the last-level cache), an odd
+ * last step then taking a one-step pass.  Health (NaN, rho <= 0, T <= 0) is
+ * recorded on the device and reported by the next synchronising call.
+ * Errors: MRT_ESTATE, MRT_EINVAL (n < 0). */
 int mrt_step(mrt_ctx* ctx, int n);
 
 /* Capture (without running anything) the HIP graphs that a following
  * mrt_step(ctx, n) will replay, so that their one-time capture and
- * instantiation cost (about a millisecond for 64 steps) falls outside a timed
- * region or a latency-critical loop.  Steps are replayed as n / 64 replays of
- * one 64-step graph and one graph of the remaining steps, per start buffer;
- * the graphs are kept until the tile, scheme or context changes.  Runs
- * nothing on the GPU; errors as mrt_step. */
+ * instantiation cost (about a millisecond for 64 passes) falls outside a timed
+ * region or a latency-critical loop.  The kernel passes of mrt_step(n) (n, or
+ * n / 2 with two steps per pass) are replayed as replays of one 64-pass graph
+ * and one graph of the remaining passes, per start buffer (an odd step of the
+ * two-step mode is launched directly); the graphs are kept until the tile,
+ * steps per pass, scheme or context changes.  Runs nothing on the GPU; errors
+ * as mrt_step. */
 int mrt_prepare_steps(mrt_ctx* ctx, int n);
 
 /* Macroscopic fields of the current populations: rho = fhat_1, u = j/rho,
@@ -163,8 +168,10 @@ int mrt_current_buffer(mrt_ctx* ctx, void** cur, void** other);
  * the flag is cleared). */
 int mrt_sync(mrt_ctx* ctx);
 
-/* Tile shape of the step kernel: rows per work item (>= 1) and workgroups
- * launched (0 = one per work item).  The defaults come from mrt_autotune. */
+/* Tile shape of the one-step kernel: rows per work item (>= 1; each work item
+ * is 256 columns, one 4-wave workgroup) and workgroups launched (0 = one per
+ * work item).  mrt_init_grid picks rows from the grid size (about 8192 work
+ * items, at most 6 rows); mrt_autotune replaces them with measured ones. */
 int mrt_set_tile(mrt_ctx* ctx, int rows_per_item, int grid_blocks);
 int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
 
@@ -205,8 +212,10 @@ int mrt_get_steps_per_pass(const mrt_ctx* ctx, int* steps, int* rows);
 #define MRT_SCHEME_LW_CROSS 2
 int mrt_set_scheme(mrt_ctx* ctx, int flags);
 
-/* Time candidate tile shapes on the current state (the populations are saved
- * and restored) and keep the fastest.  Synchronises. */
+/* Time candidate launches on the current state (the populations are saved
+ * and restored): one-step tiles (rows 1..128, grid sizes) and, for FP32
+ * storage, two steps per pass with bands of 8, 16 and 32 rows; keep the
+ * fastest per step.  Synchronises. */
 int mrt_autotune(mrt_ctx* ctx, int steps_per_trial);
 
 void mrt_destroy(mrt_ctx* ctx);
