@@ -106,6 +106,12 @@ def test_null_handles_are_rejected():
     assert lib.mrt_set_tile(None, 4, 0) == L.MRT_EINVAL
     assert lib.mrt_adjoint_step(None, None, None, None, None) == L.MRT_EINVAL
     assert lib.mrt_batch_step(None, 1) == L.MRT_EINVAL
+    assert lib.mrt_set_steps_per_pass(None, 2, 0) == L.MRT_EINVAL
+    assert lib.mrt_get_steps_per_pass(None, None, None) == L.MRT_EINVAL
+    assert lib.mrt_batch_set_steps_per_pass(None, 2, 0) == L.MRT_EINVAL
+    assert lib.mrt_batch_get_steps_per_pass(None, None, None) == L.MRT_EINVAL
+    assert lib.mrt_prepare_steps(None, 4) == L.MRT_EINVAL
+    assert lib.mrt_autotune(None, 4) == L.MRT_EINVAL
     assert lib.mrt_last_error(None) == b"NULL context"
     assert lib.mrt_batch_last_error(None) == b"NULL batch"
     lib.mrt_destroy(None)
