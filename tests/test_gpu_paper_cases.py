@@ -6,7 +6,7 @@ Parity: full-size runs against the FP64 oracle on the same inputs.  Physics:
 the paper's claim that MRT shows weaker oscillations at the discontinuities
 than SRT (section (b)), measured against the exact Riemann solution after
 the paper's 130,000 steps; and the instability of the gamma = 5/3 MRT run,
-which the oracle's linear stability analysis predicts under this build's
+which the oracle's linear stability analysis predicts under the library's
 reading of the time and space discretisation.
 """
 import functools

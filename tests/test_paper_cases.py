@@ -1,5 +1,5 @@
 """Linear stability of the paper's strong-shock configuration (section (b))
-under this build's reading of the discretisation (unsplit forward Euler,
+under the library's reading of the discretisation (unsplit forward Euler,
 per-axis Lax-Wendroff), from the oracle's amplification spectrum.  It
 explains which runs of that section survive the paper's 130,000 steps."""
 import numpy as np
