@@ -686,7 +686,9 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
     }
 
     // rm, r0, rp, rn: f^n rows y-1, y, y+1, y+2 (prefetched);
-    // q2, q1, qn: f^{n+1} rows y-2, y-1, y (qn computed here)
+    // q2, q1, qn: f^{n+1} rows y-2, y-1, y (qn computed here).  Health is
+    // accumulated per lane and reported once per item.
+    bool healthy = true;
     auto body = [&](const S (&rm)[16], const S (&r0)[16], const S (&rp)[16], S (&rn)[16],
                     const S (&q2)[16], S (&q1)[16], S (&qn)[16], int y) {
         const bool more = y < y1;
@@ -714,7 +716,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             S cdt[16];
             C rho, Pp;
             cell_collision<C, COMP>(r0, b, binv, Pc->sdt, cdt, rho, Pp);
-            if (act && y >= 0 && y < ny && !(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
+            healthy = healthy && (!(y >= 0 && y < ny) || (rho > C(0) && Pp > C(0)));
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
@@ -744,7 +746,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             S cdt[16];
             C rho, Pp;
             cell_collision<C, COMP>(q1, b, binv, Pc->sdt, cdt, rho, Pp);
-            if (act && !(rho > C(0) && Pp > C(0))) atomicOr(health, 1u);
+            healthy = healthy && rho > C(0) && Pp > C(0);
             const unsigned o = roff(y - 1);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
@@ -791,6 +793,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
         if (y > y1) break;
         body(D, A, B, Cw, F, G, H, y); ++y;
     }
+    if (act && !healthy) atomicOr(health, 1u);
 }
 
 // Two blocks (two waves per SIMD) per CU: the occupancy its ~220 VGPRs allow;
