@@ -36,15 +36,15 @@ HEADLINE_TILE_ROWS = 8              # the one-step kernel's band height for this
 # dispatch, mean over the step dispatches) of
 #   bench.py --steps 10 --warmup 2 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,316.1 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,315.7 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this band height; otherwise the roofline
 # reports traffic = null.
 MEASURED_TRAFFIC = {
-    "digest": "28dc367b7c3ca530f36fb956aedfb5dfb12e996e8d6179a581f8972afb181e4d",
+    "digest": "6435a003c30d00561f3b52aee85f8321048b235ec8de445f3bd1b66fd8752396",
     "band_rows": HEADLINE_BAND_ROWS,
-    "fetch_kib": 770469.5, "fetch_copy_kib": 524316.1,
-    "write_kib": 1048576.3, "write_copy_kib": 1048576.0,
+    "fetch_kib": 770514.3, "fetch_copy_kib": 524315.7,
+    "write_kib": 1048576.1, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
