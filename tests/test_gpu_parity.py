@@ -127,3 +127,24 @@ def test_graph_replays_equal_plain_launches(precision):
         assert np.array_equal(pa, pb), n
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp32"])
+def test_fp32_forms_after_1000_steps(precision):
+    """The FP32 forms against the FP64 oracle after 1000 steps (the stated
+    1e-5 on rho, u, T, or twice the error of FP32 storage alone where that is
+    larger), on a 1024 x 48 band of the 2D Riemann problem, with one and
+    with two steps per kernel pass."""
+    from helpers import fp32_tolerances
+    case = W.riemann2d(n=1024, ny=48, seed=0)
+    want, p = oracle_run(case, 1000)
+    tol = fp32_tolerances(case, 1000, want)
+    for per_pass in (1, 2):
+        print(f"case {case.name} {precision} 1000 steps, {per_pass} per pass", flush=True)
+        s = solver_for_case(case, precision)
+        s.set_steps_per_pass(per_pass, 16)
+        s.step(1000)
+        err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+        s.close()
+        print(precision, per_pass, "errors", err, "tolerances", tol, flush=True)
+        assert all(err[k] < tol[k] for k in err), (per_pass, err, tol)
