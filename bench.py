@@ -39,9 +39,9 @@ HEADLINE_TILE_ROWS = 8              # the one-step kernel's band height for this
 # 1 GiB device copy (FETCH_SIZE 524,315.7 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this band height; otherwise the roofline
-# reports traffic = null.
+# reports traffic = null (comments are not hashed).
 MEASURED_TRAFFIC = {
-    "digest": "6435a003c30d00561f3b52aee85f8321048b235ec8de445f3bd1b66fd8752396",
+    "digest": "56406414593c4a8468b339c85498f76763c0d6cfcdbd74ff7743bd9bf0ad2e2e",
     "band_rows": HEADLINE_BAND_ROWS,
     "fetch_kib": 770514.3, "fetch_copy_kib": 524315.7,
     "write_kib": 1048576.1, "write_copy_kib": 1048576.0,
@@ -49,11 +49,20 @@ MEASURED_TRAFFIC = {
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without comments, whitespace collapsed (so that editing a
+    comment does not invalidate a measurement)."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_digest() -> str:
-    """sha256 over what decides the step kernel's memory traffic: its source
-    (mrt_kernels.hip up to the adjoint section: helpers, ghost and step
-    kernels), its launcher, the headers it includes, and the population
-    layout (the layout functions of mrt_api.hip)."""
+    """sha256 over what decides the step kernels' memory traffic, comments
+    aside: their source (mrt_kernels.hip up to the adjoint section: helpers,
+    ghost and step kernels), their launchers, the headers they include, and
+    the population layout (the layout functions of mrt_api.hip)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1004_5442_amd", "csrc")
     with open(os.path.join(csrc, "mrt_kernels.hip")) as fh:
@@ -68,10 +77,10 @@ def kernel_digest() -> str:
     layout = api[api.index("// Population layout"):api.index("bool bc_ok(")]
     h = hashlib.sha256()
     for part in [head, *launchers, layout]:
-        h.update(hashlib.sha256(part.encode()).digest())
+        h.update(hashlib.sha256(_code_only(part).encode()).digest())
     for name in STEP_HEADERS:
-        with open(os.path.join(csrc, name), "rb") as fh:
-            h.update(hashlib.sha256(fh.read()).digest())
+        with open(os.path.join(csrc, name)) as fh:
+            h.update(hashlib.sha256(_code_only(fh.read()).encode()).digest())
     return h.hexdigest()
 
 

@@ -5,7 +5,9 @@
 //   f_i(x)^{n+1} = f_i(x) - dt C_i(f(x)) + LW_i(f)(x)
 //   C = Minv diag(s) (M f - fhat^eq(rho, j, e))        (Appendix for M, fhat^eq)
 //   LW_i = sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x))
-// is done by ONE fused kernel per step (step_kernel): a block of four waves
+// is done by ONE fused kernel per step (step_kernel), or per two steps
+// (step2_kernel, FP32 storage: f^{n+1} stays in registers; see "two steps"
+// below): a block of four waves
 // owns 256 consecutive columns of a band of rows and marches up the band,
 // keeping the rows y-1, y, y+1 of the 16 populations in registers; x
 // neighbours come from the adjacent lanes by DPP wavefront shifts and from
