@@ -233,3 +233,39 @@ def test_large_grid_with_reflecting_walls_on_every_side(precision):
                (nx // 2, 0), (0, ny // 2)]
     compare(case, s, centres, NSTEPS + 1, precision)
     s.close()
+
+
+def shock_position(row, mid):
+    """x (in cells, sub-cell by linear interpolation) where the density of a
+    row first falls below `mid` coming from the post-shock side."""
+    r = row.double().cpu().numpy()
+    i = int(np.argmax(r < mid))
+    assert i > 0
+    return (i - 1) + (r[i - 1] - mid) / (r[i - 1] - r[i])
+
+
+def test_shock_bubble_shock_moves_at_the_rankine_hugoniot_speed():
+    """Physics at full size on the benchmark's path (4096^2, FP32 storage,
+    two steps per pass): away from the bubble the Mach-5 shock is planar and
+    moves at U_s = M sqrt(gamma T1) (pre-shock gas at rest).  Its position on
+    the row y = 1/4 after 400 and 2000 steps (before anything from the bubble,
+    first struck near step 2180, can reach that row) gives the speed."""
+    n = 4096
+    case = W.shock_bubble(n=n)
+    gamma, T1 = case.gamma, 0.6
+    u_s = 5.0 * np.sqrt(gamma * T1)
+    rho_post = case.meta["post"][0]
+    mid = 0.5 * (rho_post + 1.0)
+    s = solver_for_case(case, "fp32_eq64")
+    assert s.steps_per_pass()[0] == 2
+    xs = []
+    for steps in (400, 1600):
+        print(f"case {case.name} fp32_eq64 +{steps} steps", flush=True)
+        s.step(steps)
+        rho = s.moments_device()[0]
+        xs.append(shock_position(rho[n // 4], mid))
+    s.sync()
+    s.close()
+    speed = (xs[1] - xs[0]) / n / (1600 * case.dt)
+    print("shock positions (cells)", xs, "speed", speed, "Rankine-Hugoniot", u_s, flush=True)
+    assert abs(speed / u_s - 1.0) < 5e-3, (speed, u_s)
