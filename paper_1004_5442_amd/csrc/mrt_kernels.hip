@@ -689,8 +689,16 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
 
     // rm, r0, rp, rn: f^n rows y-1, y, y+1, y+2 (prefetched);
     // q2, q1, qn: f^{n+1} rows y-2, y-1, y (qn computed here).  Health is
-    // accumulated per lane and reported once per item.
+    // accumulated per lane and reported once per item (FP64 collision;
+    // measured faster) or reported per row (pure FP32; measured faster).
     bool healthy = true;
+    auto check = [&](bool ok) {
+        if constexpr (COMP) {
+            if (act && !ok) atomicOr(health, 1u);
+        } else {
+            healthy = healthy && ok;
+        }
+    };
     auto body = [&](const S (&rm)[16], const S (&r0)[16], const S (&rp)[16], S (&rn)[16],
                     const S (&q2)[16], S (&q1)[16], S (&qn)[16], int y) {
         const bool more = y < y1;
@@ -718,7 +726,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             S cdt[16];
             C rho, Pp;
             cell_collision<C, COMP>(r0, b, binv, Pc->sdt, cdt, rho, Pp);
-            healthy = healthy && (!(y >= 0 && y < ny) || (rho > C(0) && Pp > C(0)));
+            check(!(y >= 0 && y < ny) || (rho > C(0) && Pp > C(0)));
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
@@ -748,7 +756,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             S cdt[16];
             C rho, Pp;
             cell_collision<C, COMP>(q1, b, binv, Pc->sdt, cdt, rho, Pp);
-            healthy = healthy && rho > C(0) && Pp > C(0);
+            check(rho > C(0) && Pp > C(0));
             const unsigned o = roff(y - 1);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
