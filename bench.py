@@ -36,15 +36,15 @@ HEADLINE_TILE_ROWS = 8              # the one-step kernel's band height for this
 # dispatch, mean over the step dispatches) of
 #   bench.py --steps 10 --warmup 2 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,315.7 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,315.3 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this band height; otherwise the roofline
 # reports traffic = null (comments are not hashed).
 MEASURED_TRAFFIC = {
-    "digest": "56406414593c4a8468b339c85498f76763c0d6cfcdbd74ff7743bd9bf0ad2e2e",
+    "digest": "415d7b127d2cac28acd77b7638253e4348669e5cd140af47d37162260ca1becb",
     "band_rows": HEADLINE_BAND_ROWS,
-    "fetch_kib": 770514.3, "fetch_copy_kib": 524315.7,
-    "write_kib": 1048576.1, "write_copy_kib": 1048576.0,
+    "fetch_kib": 771931.3, "fetch_copy_kib": 524315.3,
+    "write_kib": 1048576.5, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 
