@@ -130,6 +130,8 @@ int fill_inst(Inst& I, int nx, int ny, const int bc[4], const mrt_params* p, std
             I.lw[a][k][1] = 0.5 * c * c + 0.5 * c;
             I.lwf[a][k][0] = float(I.lw[a][k][0]);
             I.lwf[a][k][1] = float(I.lw[a][k][1]);
+            I.lws[a][k] = I.lw[a][k][0] + I.lw[a][k][1];
+            I.lwsf[a][k] = I.lwf[a][k][0] + I.lwf[a][k][1];
         }
     for (int k = 0; k < 4; ++k) {
         // diagonal shells: |v_x| = |v_y| = shell_speed(k)

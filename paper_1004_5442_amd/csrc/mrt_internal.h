@@ -44,6 +44,10 @@ struct Inst {
     // |c_x c_y| / 4 (zero on the axis shells)
     double lwc[4];
     float lwcf[4];
+    // lw[a][k][0] + lw[a][k][1] (c^2), summed in each precision exactly as a
+    // kernel would sum the two weights it reads
+    double lws[2][4];
+    float lwsf[2][4];
     double ghost[4][16];   // f^eq of each MRT_BC_EQ side
 };
 

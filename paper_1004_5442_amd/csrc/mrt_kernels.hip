@@ -121,36 +121,57 @@ template <>
 struct Weights<float> {
     template <typename IP>
     __device__ static float get(IP P, int ax, int k, int j) { return P->lwf[ax][k][j]; }
+    template <typename IP>
+    __device__ static float sum(IP P, int ax, int k) { return P->lwsf[ax][k]; }
     __device__ static float cross(const Inst* P, int k) { return P->lwcf[k]; }
 };
 template <>
 struct Weights<double> {
     template <typename IP>
     __device__ static double get(IP P, int ax, int k, int j) { return P->lw[ax][k][j]; }
+    template <typename IP>
+    __device__ static double sum(IP P, int ax, int k) { return P->lws[ax][k]; }
     __device__ static double cross(const Inst* P, int k) { return P->lwc[k]; }
 };
 
 // New value of population i of a site: f + LW_i(f) - dt C_i, with the
 // neighbour values W / E (x - 1 / x + 1; used if population i moves in x)
-// and So / N (y - 1 / y + 1; used if it moves in y).  The Lax-Wendroff
-// increment d = sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x)) is
-// formed as w_down f(x+e) + w_up f(x-e) - c^2 f(x) (the terms cancel to d;
-// every rounding is c times smaller than f).
+// and So / N (y - 1 / y + 1; used if it moves in y).  Per axis the
+// Lax-Wendroff increment sum_a w_down (f(x+e_a) - f(x)) + w_up (f(x-e_a) - f(x))
+// is w_down f(x+e) + w_up f(x-e) - c^2 f(x) (c^2 = w_down + w_up, summed on
+// the host in the precision of S).  The whole increment, from -dt C_i, is
+// accumulated in one chain of FMAs, so that every rounding is at the
+// magnitude of the increment, and f is added once at the end.
+template <typename S>
+__device__ __forceinline__ S fma_s(S a, S b, S c) {
+    if constexpr (sizeof(S) == 4)
+        return __builtin_fmaf(a, b, c);
+    else
+        return __builtin_fma(a, b, c);
+}
 template <typename S, typename IP>
-__device__ __forceinline__ S site_update(IP P, int i, S f, S W, S E, S So, S N, S cdt) {
+__device__ __forceinline__ S lw_increment(IP P, int i, S f, S W, S E, S So, S N, S cdt) {
     const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
-    S d = S(0);
+    S d = -cdt;
     if (sx != 0) {
         const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
         const S we = sx > 0 ? wd : wu, ww = sx > 0 ? wu : wd;
-        d = we * E + (ww * W - (wd + wu) * f);
+        d = fma_s(-Weights<S>::sum(P, 0, k), f, d);
+        d = fma_s(ww, W, d);
+        d = fma_s(we, E, d);
     }
     if (sy != 0) {
         const S wd = Weights<S>::get(P, 1, k, 0), wu = Weights<S>::get(P, 1, k, 1);
         const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
-        d += wn * N + (ws * So - (wd + wu) * f);
+        d = fma_s(-Weights<S>::sum(P, 1, k), f, d);
+        d = fma_s(ws, So, d);
+        d = fma_s(wn, N, d);
     }
-    return f + (d - cdt);
+    return d;
+}
+template <typename S, typename IP>
+__device__ __forceinline__ S site_update(IP P, int i, S f, S W, S E, S So, S N, S cdt) {
+    return f + lw_increment(P, i, f, W, E, So, N, cdt);
 }
 
 // ------------------------------------------------------------------ ghosts
@@ -526,6 +547,40 @@ __device__ __forceinline__ ConstInst* reload(ConstInst* p) {
     return reinterpret_cast<ConstInst*>(a);
 }
 
+// The march addresses population i of a row as a wave-uniform 64-bit
+// pointer (scalar registers) plus the lane's 32-bit byte offset, which the
+// memory instruction adds itself (no vector arithmetic per access).  The
+// pointer steps from population to population through an opaque register,
+// so the sixteen population bases are formed per row (two scalar adds each)
+// instead of being held, and spilled, across the march.
+using GByte = __attribute__((address_space(1))) char;
+// The lane's byte offset, re-formed where a row's accesses are issued: the
+// instruction selector takes the scalar-base form only when it sees the
+// offset as a 32-bit value in the same block.
+__device__ __forceinline__ unsigned lane_off(unsigned o) {
+    asm volatile("" : "+v"(o));
+    return o;
+}
+__device__ __forceinline__ unsigned long long next_pop(unsigned long long a, unsigned long long step) {
+    a += step;
+    asm("" : "+s"(a));
+    return a;
+}
+template <typename S>
+__device__ __forceinline__ S gload(unsigned long long a, unsigned boff) {
+    using GS = const __attribute__((address_space(1))) S;
+    return *reinterpret_cast<GS*>(reinterpret_cast<const GByte*>(a) + boff);
+}
+template <typename S, bool NT>
+__device__ __forceinline__ void gstore(unsigned long long a, unsigned boff, S v) {
+    using GS = __attribute__((address_space(1))) S;
+    GS* p = reinterpret_cast<GS*>(reinterpret_cast<GByte*>(a) + boff);
+    if constexpr (NT)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 template <typename S>
 struct EdgeBuf2 {
     S v[2][2][kWaves][2][12];      // [slot][level][wave][lane 0 / 63][x-moving population]
@@ -601,15 +656,30 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
     unsigned hx = cx;
     if (west) hx = unsigned(x0 > 0 ? x0 - 1 : P->col_lo);
     if (east) hx = unsigned(x0 + 256 < nx ? x0 + 256 : P->col_hi);
+    // Row pointers of the march point at column -1 (the west ghost column,
+    // the lowest column read: col_lo is -1 on fixed-equilibrium and
+    // reflecting sides), so the lanes' byte offsets (column + 1) * sizeof(S)
+    // are never negative; a row holds fewer than 2^28 elements, so they fit
+    // 32 bits.
+    const unsigned long long fib = reinterpret_cast<unsigned long long>(fi);
+    const unsigned long long fob = reinterpret_cast<unsigned long long>(fo);
+    const unsigned long long pstep = (unsigned long long)plane * sizeof(S);
+    const unsigned bcx = (cx + 1u) * unsigned(sizeof(S)), bhx = (hx + 1u) * unsigned(sizeof(S));
+    const unsigned bxs = (xs + 1u) * unsigned(sizeof(S));
+    auto row_at = [&](unsigned long long base, unsigned o) {
+        return base + ((unsigned long long)o - 1u) * sizeof(S);
+    };
     const bool edge_lane = lane == 0 || lane == 63;
     const int eside = lane == 0 ? 0 : 1;
     const int nwave = lane == 0 ? wv - 1 : wv + 1;
     const int nside = lane == 0 ? 1 : 0;
     const bool hlds = edge_lane && !hmem;
-    // east f^{n+1} neighbour of the last grid column when it lies inside a
-    // wave (the DPP shift would bring the value of a lane past the grid)
+    // When the grid ends inside the block, the first lane past it (x = nx,
+    // inactive) holds the east halo column's f^{n+1} of the rows the block
+    // advances, so that the DPP shift or the neighbour wave hands the last
+    // grid column that value as its east neighbour.
     const int xe = x0 + 256 < nx ? x0 + 256 : nx;
-    const bool east_mid = x == xe - 1 && !east;
+    const bool east_src = x == xe;
     const bool per_lo = P->bc[YLO] == BC_PERIODIC, per_hi = P->bc[YHI] == BC_PERIODIC;
     // row offsets from values read once per item (the march reads the
     // instance only through reload(); periodic sides wrap two rows deep,
@@ -703,9 +773,13 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
                     const S (&q2)[16], S (&q1)[16], S (&qn)[16], int y) {
         const bool more = y < y1;
         if (more) {
-            const unsigned on = roff2(y + 2);
+            unsigned long long a = row_at(fib, roff2(y + 2));
+            const unsigned bo = lane_off(bcx);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) rn[i] = ld(i, on, cx);
+            for (int i = 0; i < 16; ++i) {
+                rn[i] = gload<S>(a, bo);
+                if (i < 15) a = next_pop(a, pstep);
+            }
         }
         // f^{n+1}, row y
         {
@@ -715,9 +789,13 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
 #pragma unroll
             for (int i = 0; i < 16; ++i) h[i] = S(0);
             if (hmem) {
+                unsigned long long a = row_at(fib, o);
+                const unsigned bo = lane_off(bhx);
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (moves_x(i)) h[i] = ld(i, o, hx);
+                for (int i = 0; i < 16; ++i) {
+                    if (moves_x(i)) h[i] = gload<S>(a, bo);
+                    if (i < 15) a = next_pop(a, pstep);
+                }
             } else if (hlds) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
@@ -732,6 +810,11 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
                 const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
                 const S E = moves_x(i) ? from_right(r0[i], h[i]) : S(0);
                 qn[i] = site_update(Pc, i, r0[i], W, E, rm[i], rp[i], cdt[i]);
+            }
+            if (east_src && y >= y0 && y < y1) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) qn[i] = lds.halo[1][y - y0][xslot(i)];
             }
         }
         // ghost rows of f^{n+1} on non-periodic y sides
@@ -757,18 +840,14 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             C rho, Pp;
             cell_collision<C, COMP>(q1, b, binv, Pc->sdt, cdt, rho, Pp);
             check(rho > C(0) && Pp > C(0));
-            const unsigned o = roff(y - 1);
+            unsigned long long a = row_at(fob, roff(y - 1));
+            const unsigned bo = lane_off(bxs);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const S W = moves_x(i) ? from_left(q1[i], h[i]) : S(0);
-                S E = moves_x(i) ? from_right(q1[i], h[i]) : S(0);
-                if (moves_x(i) && east_mid) E = lds.halo[1][r][xslot(i)];
-                S* dst = &(fo + (long long)i * plane)[o + xs];
-                const S v = site_update(Pc, i, q1[i], W, E, q2[i], qn[i], cdt[i]);
-                if constexpr (NT)
-                    __builtin_nontemporal_store(v, dst);
-                else
-                    *dst = v;
+                const S E = moves_x(i) ? from_right(q1[i], h[i]) : S(0);
+                gstore<S, NT>(a, bo, site_update(Pc, i, q1[i], W, E, q2[i], qn[i], cdt[i]));
+                if (i < 15) a = next_pop(a, pstep);
             }
         }
         // hand the edge values of f^n row y+1 and f^{n+1} row y to the
@@ -1039,29 +1118,21 @@ __global__ __launch_bounds__(256) void cell_step_kernel(const Inst* __restrict__
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
-            S d = S(0);
-            if (sx != 0) {
-                const S E = ld(i, o, xe), W = ld(i, o, xw);
-                const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
-                const S we = sx > 0 ? wd : wu, ww = sx > 0 ? wu : wd;
-                d = we * E + (ww * W - (wd + wu) * f[i]);
-            }
-            if (sy != 0) {
-                const S N = ld(i, on, xc), So = ld(i, os, xc);
-                const S wd = Weights<S>::get(P, 1, k, 0), wu = Weights<S>::get(P, 1, k, 1);
-                const S wn = sy > 0 ? wd : wu, ws = sy > 0 ? wu : wd;
-                d += wn * N + (ws * So - (wd + wu) * f[i]);
-            }
+            const S E = sx != 0 ? ld(i, o, xe) : S(0), W = sx != 0 ? ld(i, o, xw) : S(0);
+            const S N = sy != 0 ? ld(i, on, xc) : S(0), So = sy != 0 ? ld(i, os, xc) : S(0);
+            // the per-axis increment exactly as the marching kernels form it;
+            // the mixed-derivative term (nine-point stencil) is added last
+            S d = lw_increment(P, i, f[i], W, E, So, N, cdt[i]);
             if constexpr (CROSS) {
                 if (sx != 0 && sy != 0) {
                     const S ne = ld(i, on, xe), nw = ld(i, on, xw);
                     const S se = ld(i, os, xe), sw = ld(i, os, xw);
                     const S wc = Weights<S>::cross(P, k);
                     const S sxy = S(sx * sy);
-                    d += sxy * wc * ((ne - nw) - (se - sw));
+                    d = fma_s(sxy * wc, (ne - nw) - (se - sw), d);
                 }
             }
-            (fo + (long long)i * plane)[o + xc] = f[i] + (d - cdt[i]);
+            (fo + (long long)i * plane)[o + xc] = f[i] + d;
         }
     }
 }

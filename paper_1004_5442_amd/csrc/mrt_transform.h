@@ -26,6 +26,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #define MRT_HD __host__ __device__ __forceinline__
 
 namespace mrt {
@@ -89,16 +91,20 @@ MRT_HD void pops_to_moments(const C f[16], C m[16]) {
 // m (16) -> f (16): f = Minv m.
 template <typename C>
 MRT_HD void moments_to_pops(const C m[16], C f[16]) {
-    const C R2 = C(kR2);
+    // Binv, then the inverse butterfly.  The butterfly's factors (1/4 on the
+    // shell sums and quadrupole sums, 1/2 on the axis shells' signed sums,
+    // 1/4 on the diagonal shells' signed sums) are carried in the Binv
+    // constants: scaling by a power of two is exact, so the result is the
+    // same as applying them after the sums.
+    const C R2q = C(0.25 * kR2);
     C sg[4], X[4], Y[4], Q[4];
-    sg[0] = C(0.16) * (m[3] - m[4]);
-    sg[1] = m[0] * C(1.0 / 24.0) - C(121.0 / 21600.0) * m[3] - C(17.0 / 1800.0) * m[4]
-          + C(1.0 / 864.0) * m[13];
-    sg[2] = C(81.0 / 40.0) * m[0] - C(229.0 / 800.0) * m[3] + C(1.0 / 200.0) * m[4]
-          + C(1.0 / 160.0) * m[13];
-    sg[3] = C(-16.0 / 15.0) * m[0] + C(89.0 / 675.0) * m[3] + C(37.0 / 225.0) * m[4]
-          - C(1.0 / 135.0) * m[13];
-    // x-odd (m2, m8, m10, m12) and y-odd (m3, m9, m11, -m13) share one inverse
+    sg[0] = C(0.25 * 0.16) * (m[3] - m[4]);
+    sg[1] = m[0] * C(0.25 / 24.0) - C(0.25 * (121.0 / 21600.0)) * m[3]
+          - C(0.25 * (17.0 / 1800.0)) * m[4] + C(0.25 / 864.0) * m[13];
+    sg[2] = C(0.25 * (81.0 / 40.0)) * m[0] - C(0.25 * (229.0 / 800.0)) * m[3]
+          + C(0.25 / 200.0) * m[4] + C(0.25 / 160.0) * m[13];
+    sg[3] = C(0.25 * (-16.0 / 15.0)) * m[0] + C(0.25 * (89.0 / 675.0)) * m[3]
+          + C(0.25 * (37.0 / 225.0)) * m[4] - C(0.25 / 135.0) * m[13];
     const C xa[4] = {m[1], m[7], m[9], m[11]};
     const C ya[4] = {m[2], m[8], m[10], -m[12]};
     const C* src[2] = {xa, ya};
@@ -107,39 +113,35 @@ MRT_HD void moments_to_pops(const C m[16], C f[16]) {
     for (int a = 0; a < 2; ++a) {
         const C* s = src[a];
         C* d = dst[a];
-        d[0] = C(0.16) * (s[1] - s[2]);
-        d[1] = (s[2] - s[1]) * C(1.0 / 1350.0) + s[3] * C(1.0 / 216.0);
-        d[2] = R2 * (C(0.9) * s[0] - C(0.14) * s[1] + C(0.04) * s[2] + C(0.075) * s[3]);
-        d[3] = R2 * (C(-4.0 / 15.0) * s[0] + C(28.0 / 675.0) * s[1] + C(17.0 / 675.0) * s[2]
-                     - C(8.0 / 135.0) * s[3]);
+        d[0] = C(0.5 * 0.16) * (s[1] - s[2]);
+        d[1] = (s[2] - s[1]) * C(0.5 / 1350.0) + s[3] * C(0.5 / 216.0);
+        d[2] = R2q * (C(0.9) * s[0] - C(0.14) * s[1] + C(0.04) * s[2] + C(0.075) * s[3]);
+        d[3] = R2q * (C(-4.0 / 15.0) * s[0] + C(28.0 / 675.0) * s[1] + C(17.0 / 675.0) * s[2]
+                      - C(8.0 / 135.0) * s[3]);
     }
-    Q[0] = C(144.0 / 115.0) * m[5] - C(4.0 / 115.0) * m[15];
-    Q[1] = C(-29.0 / 4140.0) * m[5] + C(1.0 / 1035.0) * m[15];
-    Q[2] = C(0.9) * m[6] - C(0.1) * m[14];
-    Q[3] = C(-8.0 / 45.0) * m[6] + C(2.0 / 45.0) * m[14];
+    Q[0] = C(0.25 * (144.0 / 115.0)) * m[5] - C(0.25 * (4.0 / 115.0)) * m[15];
+    Q[1] = C(0.25 * (-29.0 / 4140.0)) * m[5] + C(0.25 / 1035.0) * m[15];
+    Q[2] = C(0.25 * 0.9) * m[6] - C(0.25 * 0.1) * m[14];
+    Q[3] = C(0.25 * (-8.0 / 45.0)) * m[6] + C(0.25 * (2.0 / 45.0)) * m[14];
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
-        const C sp = C(0.25) * (sg[k] + Q[k]), sm = C(0.25) * (sg[k] - Q[k]);
-        const C hx = C(0.5) * X[k], hy = C(0.5) * Y[k];
-        f[4 * k] = sp + hx;
-        f[4 * k + 1] = sm + hy;
-        f[4 * k + 2] = sp - hx;
-        f[4 * k + 3] = sm - hy;
+        const C sp = sg[k] + Q[k], sm = sg[k] - Q[k];
+        f[4 * k] = sp + X[k];
+        f[4 * k + 1] = sm + Y[k];
+        f[4 * k + 2] = sp - X[k];
+        f[4 * k + 3] = sm - Y[k];
     }
 #pragma unroll
     for (int k = 2; k < 4; ++k) {
         const C sq = sg[k] + Q[k], dq = sg[k] - Q[k];
         const C xy = X[k] + Y[k], yx = Y[k] - X[k];
-        f[4 * k] = C(0.25) * (sq + xy);
-        f[4 * k + 1] = C(0.25) * (dq + yx);
-        f[4 * k + 2] = C(0.25) * (sq - xy);
-        f[4 * k + 3] = C(0.25) * (dq - yx);
+        f[4 * k] = sq + xy;
+        f[4 * k + 1] = dq + yx;
+        f[4 * k + 2] = sq - xy;
+        f[4 * k + 3] = dq - yx;
     }
 }
 
-// z (moment space, 16) -> M^T z (population space, 16): entry i is
-// sum_k z_k m_k(v_i), i.e. the moment polynomials evaluated at velocity i.
-// Written as B^T (block columns) followed by the transposed butterfly.
 template <typename C>
 MRT_HD void moments_T(const C z[16], C g[16]) {
     const C R2 = C(kR2), R32 = C(kR32);
@@ -239,9 +241,25 @@ MRT_HD void inverse_T(const C l[16], C z[16]) {
 //   15: ((b+4)P + rho u^2) ux uy     16: ((b+4)P + rho u^2)(ux^2 - uy^2)
 // Entries 0..3 are set to the conserved moments themselves.  binv = 1/b.
 // Returns P.
+// 1/x.  FP64 on the device: the hardware reciprocal refined by two Newton
+// steps r <- r + r (1 - x r) (within an ulp of the rounded quotient, half
+// the instructions of the IEEE division sequence); other types divide.
+template <typename C>
+MRT_HD C recip(C x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    if constexpr (std::is_same<C, double>::value) {
+        double r = __builtin_amdgcn_rcp(x);
+        r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+        r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+        return r;
+    }
+#endif
+    return C(1) / x;
+}
+
 template <typename C>
 MRT_HD C equilibrium_moments(C rho, C jx, C jy, C e, C b, C binv, C eq[16]) {
-    const C ri = C(1) / rho;
+    const C ri = recip(rho);
     const C ux = jx * ri, uy = jy * ri;
     const C u2 = ux * ux + uy * uy;
     const C rhou2 = rho * u2;
