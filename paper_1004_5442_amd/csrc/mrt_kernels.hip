@@ -62,6 +62,16 @@ __device__ __forceinline__ double from_right(double v, double old) {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
+// The x neighbours that lanes 0 and 63 take from outside their wave are the
+// values the DPP shifts keep in the lane that has no source lane; the
+// marching kernels assign them in those two lanes only.  Every other lane
+// leaves them unassigned (they are passed to the shift, which overwrites
+// them there): zero-filling them cost 12 vector instructions per cell.
+template <typename S>
+__device__ __forceinline__ void no_value(S (&h)[16]) {
+    (void)h;
+}
+
 // -------------------------------------------------------------- populations
 
 constexpr bool moves_x(int i) { return i < 8 ? (i & 1) == 0 : true; }
@@ -384,8 +394,7 @@ __device__ __forceinline__ void step_block(const Inst* __restrict__ P, int x0, i
         }
         const unsigned o = row_offset(P, y);
         S h[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) h[i] = S(0);
+        no_value(h);
         if (hmem) {
 #pragma unroll
             for (int i = 0; i < 16; ++i)
@@ -786,8 +795,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             ConstInst* __restrict__ Pc = reload(P);
             const unsigned o = roff2(y);
             S h[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) h[i] = S(0);
+            no_value(h);
             if (hmem) {
                 unsigned long long a = row_at(fib, o);
                 const unsigned bo = lane_off(bhx);
@@ -825,8 +833,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             ConstInst* __restrict__ Pc = reload(P);
             const int r = y - 1 - y0;
             S h[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) h[i] = S(0);
+            no_value(h);
             if (hmem) {
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
