@@ -24,7 +24,7 @@ hipError_t k_ghost(int prec, const Inst* insts, int count, int perim, void* f, i
 hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                   void* fout, unsigned* health, int grid, bool nt, bool walls, hipStream_t st);
 hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                   void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
+                   void* fout, unsigned* health, int grid, bool nt, bool wrap4, hipStream_t st);
 hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool reflect,
                      const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
@@ -293,6 +293,7 @@ struct mrt_ctx {
     int per_pass = 1;                // time steps per pass of the marching kernel (1 or 2)
     Item* d_items2 = nullptr;        // work items of the two-step kernel
     int nitems2 = 0, rows2 = 0;
+    bool wrap4 = false;              // a two-step band is a whole periodic height of 4 rows
     GraphCache graphs2;              // captured two-step passes
     bool eager = false;              // launch step by step (the tile autotuner)
     int scheme = 0;                  // MRT_SCHEME_* flags
@@ -344,6 +345,13 @@ int build_items(mrt_ctx* c, int rows) {
 }
 
 // Work items of the two-step kernel: bands of `rows` <= 32 rows.
+// Whether the two-step bands of an instance with band height `rows` are a
+// whole periodic height of four rows (the march then reuses f^{n+1} of the
+// wrapped rows; mrt_kernels.hip, step2_block).
+bool wraps_four_rows(const Inst& I, int rows) {
+    return I.ny == 4 && rows >= 4 && I.bc[2] == MRT_BC_PERIODIC && I.bc[3] == MRT_BC_PERIODIC;
+}
+
 int build_items2(mrt_ctx* c, int rows) {
     std::string& ctx_err = c->err;
     std::vector<Item> items;
@@ -354,6 +362,7 @@ int build_items2(mrt_ctx* c, int rows) {
     HIPTRY(hipMemcpy(c->d_items2, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
     c->nitems2 = int(items.size());
     c->rows2 = rows;
+    c->wrap4 = wraps_four_rows(c->inst, rows);
     c->graphs2.clear();
     return MRT_OK;
 }
@@ -550,7 +559,7 @@ static int step_impl(mrt_ctx* c, int n, bool launch) {
                 if (e != hipSuccess) return e;
             }
             return mrt::k_step2(c->prec, c->d_inst, c->d_items2, c->nitems2, c->f[cur], c->f[1 - cur],
-                                c->d_health, 0, c->nt, st);
+                                c->d_health, 0, c->nt, c->wrap4, st);
         };
         auto enqueue1 = [&](int cur, hipStream_t st) -> hipError_t {
             if (reflect) {
@@ -1029,6 +1038,7 @@ struct mrt_batch {
     int per_pass = 1;                       // time steps per pass (1 or 2)
     Item* d_items2 = nullptr;               // work items of the two-step kernel
     int nitems2 = 0, rows2 = 0;
+    bool wrap4 = false;                     // some band is a whole periodic height of 4 rows
     GraphCache graphs2;                     // captured two-step passes
     std::string err;
 };
@@ -1065,6 +1075,8 @@ int batch_items2(mrt_batch* b, int rows) {
     HIPTRY(hipMemcpy(b->d_items2, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
     b->nitems2 = int(items.size());
     b->rows2 = rows;
+    b->wrap4 = false;
+    for (int i = 0; i < b->count; ++i) b->wrap4 = b->wrap4 || wraps_four_rows(b->insts[i], rows);
     b->graphs2.clear();
     return MRT_OK;
 }
@@ -1186,7 +1198,7 @@ static int batch_step_impl(mrt_batch* b, int n, bool launch) {
             const hipError_t e = ghosts(cur, st);
             if (e != hipSuccess) return e;
             return mrt::k_step2(b->prec, b->d_insts, b->d_items2, b->nitems2, b->f[cur], b->f[1 - cur],
-                                b->d_health, 0, b->nt, st);
+                                b->d_health, 0, b->nt, b->wrap4, st);
         };
         const int pairs = n / 2;
         if (pairs > 0) HIPTRY(run_graphs(b->graphs2, b->cur, pairs, b->stream, enqueue2, launch));

@@ -642,7 +642,7 @@ __device__ __forceinline__ void ghost_row_rule(ConstInst* __restrict__ P, int si
     }
 }
 
-template <typename S, typename C, bool COMP, bool NT>
+template <typename S, typename C, bool COMP, bool NT, bool W4>
 __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, int y0, int y1,
                                             const S* __restrict__ fin, S* __restrict__ fout,
                                             unsigned* __restrict__ health, EdgeBuf2<S>& lds) {
@@ -690,6 +690,10 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
     const int xe = x0 + 256 < nx ? x0 + 256 : nx;
     const bool east_src = x == xe;
     const bool per_lo = P->bc[YLO] == BC_PERIODIC, per_hi = P->bc[YHI] == BC_PERIODIC;
+    // W4: the launch holds bands that are a whole periodic height of four
+    // rows (a separate instantiation, so that other launches keep the
+    // registers and schedule of the plain march)
+    const bool wrap4 = W4 && per_lo && per_hi && y0 == 0 && y1 == ny && ny == 4;
     // row offsets from values read once per item (the march reads the
     // instance only through reload(); periodic sides wrap two rows deep,
     // other sides go through the one-deep remap: rows -2 / ny + 1 are then
@@ -781,7 +785,15 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
     auto body = [&](const S (&rm)[16], const S (&r0)[16], const S (&rp)[16], S (&rn)[16],
                     const S (&q2)[16], S (&q1)[16], S (&qn)[16], int y) {
         const bool more = y < y1;
-        if (more) {
+        // A band that is a whole periodic height of four rows already holds
+        // what the march would compute or load from row y1 - 1 on, in the
+        // register sets those rows rotate into: f^{n+1} of rows y1 - 1 and
+        // y1 (the wrapped rows y0 - 1 and y0, computed first) and f^n of
+        // rows y0 + 2 and y0 + 3 (the wrapped rows y0 - 2 and y0 - 1, loaded
+        // first).  Such a band loads each f^n row once and computes each
+        // f^{n+1} row once.
+        const bool fresh = !(wrap4 && y >= y1 - 1);
+        if (more && !(wrap4 && y >= y0)) {
             unsigned long long a = row_at(fib, roff2(y + 2));
             const unsigned bo = lane_off(bcx);
 #pragma unroll
@@ -791,7 +803,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             }
         }
         // f^{n+1}, row y
-        {
+        if (fresh) {
             ConstInst* __restrict__ Pc = reload(P);
             const unsigned o = roff2(y);
             S h[16];
@@ -812,18 +824,18 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
             S cdt[16];
             C rho, Pp;
             cell_collision<C, COMP>(r0, b, binv, Pc->sdt, cdt, rho, Pp);
-            check(!(y >= 0 && y < ny) || (rho > C(0) && Pp > C(0)));
+            check(!((y >= 0 && y < ny) || wrap4) || (rho > C(0) && Pp > C(0)));
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
                 const S E = moves_x(i) ? from_right(r0[i], h[i]) : S(0);
                 qn[i] = site_update(Pc, i, r0[i], W, E, rm[i], rp[i], cdt[i]);
             }
-            if (east_src && y >= y0 && y < y1) {
+        }
+        if (east_src && y >= y0 && y < y1) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    if (moves_x(i)) qn[i] = lds.halo[1][y - y0][xslot(i)];
-            }
+            for (int i = 0; i < 16; ++i)
+                if (moves_x(i)) qn[i] = lds.halo[1][y - y0][xslot(i)];
         }
         // ghost rows of f^{n+1} on non-periodic y sides
         if (y == 0 && !per_lo) ghost_row_rule<S, C>(P, YLO, qn, b, binv, q1);
@@ -871,7 +883,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
         const unsigned om = roff2(y0 - 2), o0 = roff2(y0 - 1), op = roff2(y0);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            A[i] = moves_y(i) ? ld(i, om, cx) : S(0);
+            A[i] = (moves_y(i) || wrap4) ? ld(i, om, cx) : S(0);
             B[i] = ld(i, o0, cx);
             Cw[i] = ld(i, op, cx);
             D[i] = E[i] = F[i] = G[i] = H[i] = S(0);
@@ -894,7 +906,7 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
 
 // Two blocks (two waves per SIMD) per CU: the occupancy its ~220 VGPRs allow;
 // stating it let the compiler schedule for it (measured 1 % faster).
-template <typename S, typename C, bool COMP, bool NT>
+template <typename S, typename C, bool COMP, bool NT, bool W4>
 __global__ __launch_bounds__(256, 2) void step2_kernel(const Inst* __restrict__ insts,
                                                     const Item* __restrict__ items, int nitems,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
@@ -910,7 +922,7 @@ __global__ __launch_bounds__(256, 2) void step2_kernel(const Inst* __restrict__ 
         const int w = (q & 7) * per + (q >> 3);
         if (w >= nitems) continue;
         const int inst = citems[w].inst, x0 = citems[w].x0, y0 = citems[w].y0, y1 = citems[w].y1;
-        step2_block<S, C, COMP, NT>(cinsts + inst, x0, y0, y1, fin, fout, health, lds);
+        step2_block<S, C, COMP, NT, W4>(cinsts + inst, x0, y0, y1, fin, fout, health, lds);
         __syncthreads();   // the next item reuses the LDS buffers
     }
 }
@@ -1294,17 +1306,26 @@ hipError_t launch_step(const Inst* insts, const Item* items, int nitems, const v
     return hipGetLastError();
 }
 
+template <typename S, typename C, bool COMP, bool NT>
+void launch_step2_w(const Inst* insts, const Item* items, int nitems, const void* fin, void* fout,
+                    unsigned* health, int blocks, bool wrap4, hipStream_t st) {
+    if (wrap4)
+        hipLaunchKernelGGL((step2_kernel<S, C, COMP, NT, true>), dim3(blocks), dim3(256), 0, st, insts,
+                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+    else
+        hipLaunchKernelGGL((step2_kernel<S, C, COMP, NT, false>), dim3(blocks), dim3(256), 0, st, insts,
+                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+}
+
 template <typename S, typename C, bool COMP>
 hipError_t launch_step2(const Inst* insts, const Item* items, int nitems, const void* fin,
-                        void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+                        void* fout, unsigned* health, int grid, bool nt, bool wrap4, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
     const int blocks = grid > 0 ? grid : 8 * ((nitems + 7) / 8);
     if (nt)
-        hipLaunchKernelGGL((step2_kernel<S, C, COMP, true>), dim3(blocks), dim3(256), 0, st, insts,
-                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+        launch_step2_w<S, C, COMP, true>(insts, items, nitems, fin, fout, health, blocks, wrap4, st);
     else
-        hipLaunchKernelGGL((step2_kernel<S, C, COMP, false>), dim3(blocks), dim3(256), 0, st, insts,
-                           items, nitems, static_cast<const S*>(fin), static_cast<S*>(fout), health);
+        launch_step2_w<S, C, COMP, false>(insts, items, nitems, fin, fout, health, blocks, wrap4, st);
     return hipGetLastError();
 }
 
@@ -1345,12 +1366,13 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
 }
 
 // Two steps from fin to fout (FP32 storage forms only; bands of at most
-// kBand2 rows); the reflecting-wall ghosts of fin must be current.
+// kBand2 rows); the reflecting-wall ghosts of fin must be current.  wrap4:
+// some item is a band that is a whole periodic height of four rows.
 hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                   void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+                   void* fout, unsigned* health, int grid, bool nt, bool wrap4, hipStream_t st) {
     switch (prec) {
-        case 1: return launch_step2<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, st);
-        case 2: return launch_step2<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        case 1: return launch_step2<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
+        case 2: return launch_step2<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
         default: return hipErrorInvalidValue;
     }
 }

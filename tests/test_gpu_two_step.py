@@ -33,8 +33,12 @@ BC_SETS = [
     ("outflow", "reflect", "eq", "outflow"),
     ("periodic", "periodic", "reflect", "eq"),
 ]
+# (257, 4) and (1, 4) with 4-row bands: where both y sides are periodic the
+# band is a whole periodic height of four rows, and the kernel takes f^{n+1}
+# of its last two rows from the wrapped rows it computed first
 SHAPES = [((150, 37), 8), ((64, 5), 2), ((1, 7), 3), ((65, 1), 1), ((256, 12), 5),
-          ((257, 9), 32), ((512, 3), 1), ((300, 40), 32), ((2, 2), 1)]
+          ((257, 9), 32), ((512, 3), 1), ((300, 40), 32), ((2, 2), 1), ((257, 4), 4),
+          ((1, 4), 4)]
 
 
 def close_to_single_step(a, b):
@@ -112,6 +116,25 @@ def test_health_flag_in_two_step_pass():
     s.set_steps_per_pass(2, 0)
     f = s.populations()
     f[:, 4, 33] = np.nan
+    s.set_populations(f)
+    s.step(2)
+    with pytest.raises(UnstableError):
+        s.moments()
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp32"])
+@pytest.mark.parametrize("row", [0, 3])
+def test_health_flag_in_wrapped_four_row_band(precision, row):
+    """A NaN in row 0 or row 3 of a 4-row periodic grid stepped in one 4-row
+    band (row 3's f^{n+1} is then computed only as the wrapped row -1)."""
+    from paper_1004_5442_amd.lib import UnstableError
+    case = smooth_case(300, 4, BC_SETS[0], seed=2)
+    print(f"case {case.name} {precision} NaN in row {row}", flush=True)
+    s = solver_for_case(case, precision)
+    s.set_steps_per_pass(2, 4)
+    f = s.populations()
+    f[:, row, 257] = np.nan
     s.set_populations(f)
     s.step(2)
     with pytest.raises(UnstableError):
