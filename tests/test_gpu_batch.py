@@ -53,19 +53,28 @@ def test_tube_batch_fp32_matches_oracle(precision):
         assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
 
 
-@pytest.mark.parametrize("rows", [4, 32])
-def test_two_step_batch_matches_oracle_and_single_step(rows):
+@pytest.mark.parametrize("precision,rows", [("fp32_eq64", 4), ("fp32_eq64", 32), ("fp32", 4)])
+def test_two_step_batch_matches_oracle_and_single_step(precision, rows):
     """Two steps per pass over the mixed batch (ragged sizes, every
     boundary kind, a one-column and a one-row instance, gamma 5/3 and
     tubes), 13 steps per call (six passes and a one-step pass) over three
-    calls, against the oracle and the one-step batch."""
+    calls, against the oracle and the one-step batch.  The 4-row tubes and
+    the 200 x 4 instance are periodic in y: their bands are a whole periodic
+    height of four rows (the wrapped-band form of the two-step kernel).
+    With the FP64 collision the two paths agree to a few FP32 roundings (on
+    these instances measured bit-identical, at any band height).  Pure FP32
+    computes the collision in FP32, where the compiler may contract products
+    and sums into FMAs differently in each unrolled row of the march, so a
+    row's rounding depends on its place in the band (measured up to 3.9e-6
+    of the populations after 39 steps on the strongest tube, at any band
+    height): there the paths' fields are compared with the FP32 tolerance."""
     cases = _mixed_cases()
-    one = Batch(cases, "fp32_eq64")
-    two = Batch(cases, "fp32_eq64")
+    one = Batch(cases, precision)
+    two = Batch(cases, precision)
     two.set_steps_per_pass(2, rows)
     assert two.steps_per_pass() == (2, rows)
     for call in range(3):
-        print(f"call {call} rows {rows}", flush=True)
+        print(f"call {call} {precision} rows {rows}", flush=True)
         one.step(13)
         two.step(13)
     for i, c in enumerate(cases):
@@ -76,7 +85,11 @@ def test_two_step_batch_matches_oracle_and_single_step(rows):
         d = float(np.max(np.abs(a - b)) / np.abs(b).max())
         print(c.name, err, "vs one step", d, flush=True)
         assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
-        assert d < 1e-6, (c.name, d)
+        if precision == "fp32_eq64":
+            assert d < 1e-6, (c.name, d)
+        else:
+            e2 = field_errors(two.moments(i), one.moments(i))
+            assert all(e2[k] < tol[k] for k in e2), (c.name, e2, tol)
 
 
 def test_batch_autotune_after_two_step_passes():
