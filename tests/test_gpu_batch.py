@@ -92,6 +92,27 @@ def test_two_step_batch_matches_oracle_and_single_step(precision, rows):
             assert all(e2[k] < tol[k] for k in e2), (c.name, e2, tol)
 
 
+def test_wrapped_four_row_bands_match_plain_bands():
+    """FP32 storage with FP64 collision: bands that are a whole periodic
+    height of four rows (f^{n+1} and f^n of their last rows taken from the
+    wrapped rows computed and loaded first) against two-row bands of the
+    plain march, over 21 steps of tubes of one to three column chunks.  The
+    per-cell arithmetic is the same, so the populations agree to the last
+    FP32 bits (measured bit-identical); the bound allows two ulps."""
+    cases = W.tube_batch(6, seed=11, nx_range=(200, 700))
+    wrapped = Batch(cases, "fp32_eq64")
+    wrapped.set_steps_per_pass(2, 4)
+    plain = Batch(cases, "fp32_eq64")
+    plain.set_steps_per_pass(2, 2)
+    wrapped.step(21)
+    plain.step(21)
+    for i, c in enumerate(cases):
+        a, b = wrapped.populations(i), plain.populations(i)
+        d = float(np.max(np.abs(a - b)) / np.abs(b).max())
+        print(c.name, c.nx, "wrapped vs plain bands", d, flush=True)
+        assert d <= 2.4e-7, (c.name, d)
+
+
 def test_batch_autotune_after_two_step_passes():
     """As for a single grid: the batch autotuner refreshes the reflecting
     ghosts that two-step passes left stale before it times and restores."""
