@@ -904,8 +904,9 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
     if (act && !healthy) atomicOr(health, 1u);
 }
 
-// Two blocks (two waves per SIMD) per CU: the occupancy its ~220 VGPRs allow;
-// stating it let the compiler schedule for it (measured 1 % faster).
+// Two blocks (two waves per SIMD) per CU: the occupancy its 213-249 VGPRs
+// (by form) allow; stating it let the compiler schedule for it (measured
+// 1 % faster).
 template <typename S, typename C, bool COMP, bool NT, bool W4>
 __global__ __launch_bounds__(256, 2) void step2_kernel(const Inst* __restrict__ insts,
                                                     const Item* __restrict__ items, int nitems,
