@@ -735,44 +735,50 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
         }
     };
 
-    // f^{n+1} of the halo columns, rows [y0, y1): lanes 0-31 west, 32-63 east
-    if (wv == 0) {
-        const int side = lane >> 5, r = lane & 31, y = y0 + r;
-        if (y < y1) {
-            const int hc = side == 0 ? x0 - 1 : xe;
-            const int bside = side == 0 ? XLO : XHI;
-            int src = hc, rule = 0;          // 0: f^{n+1}(src); 1: its reflection; 2: equilibrium
-            if (hc < 0 || hc >= nx) {
-                const int kind = P->bc[bside];
-                if (kind == BC_PERIODIC) {
-                    src = side == 0 ? nx - 1 : 0;
-                } else if (kind == BC_EQ) {
-                    rule = 2;
-                } else {
-                    src = side == 0 ? 0 : nx - 1;
-                    rule = kind == BC_REFLECT ? 1 : 0;
+    // f^{n+1} of the halo columns, rows [y0, y1) (wave 0): run before the
+    // initial row loads, or, where the launch holds four-row periodic bands
+    // (short marches whose start is not hidden), after them, so that wave
+    // 0's row loads are in flight during it
+    auto halo_prologue = [&]() {
+        // lanes 0-31 west, 32-63 east
+        if (wv == 0) {
+            const int side = lane >> 5, r = lane & 31, y = y0 + r;
+            if (y < y1) {
+                const int hc = side == 0 ? x0 - 1 : xe;
+                const int bside = side == 0 ? XLO : XHI;
+                int src = hc, rule = 0;          // 0: f^{n+1}(src); 1: its reflection; 2: equilibrium
+                if (hc < 0 || hc >= nx) {
+                    const int kind = P->bc[bside];
+                    if (kind == BC_PERIODIC) {
+                        src = side == 0 ? nx - 1 : 0;
+                    } else if (kind == BC_EQ) {
+                        rule = 2;
+                    } else {
+                        src = side == 0 ? 0 : nx - 1;
+                        rule = kind == BC_REFLECT ? 1 : 0;
+                    }
                 }
-            }
-            S g[16];
-            if (rule == 2) {
+                S g[16];
+                if (rule == 2) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[bside][i]);
-            } else {
-                S u[16];
-                cell_update<S, C, COMP>(P, fi, src, y, b, binv, u);
-                if (rule == 1) {
-                    reflected_eq<C>(u, 0, b, binv, g);
+                    for (int i = 0; i < 16; ++i) g[i] = S(P->ghost[bside][i]);
                 } else {
+                    S u[16];
+                    cell_update<S, C, COMP>(P, fi, src, y, b, binv, u);
+                    if (rule == 1) {
+                        reflected_eq<C>(u, 0, b, binv, g);
+                    } else {
 #pragma unroll
-                    for (int i = 0; i < 16; ++i) g[i] = u[i];
+                        for (int i = 0; i < 16; ++i) g[i] = u[i];
+                    }
                 }
-            }
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (moves_x(i)) lds.halo[side][r][xslot(i)] = g[i];
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) lds.halo[side][r][xslot(i)] = g[i];
+            }
         }
-    }
-
+    };
+    if constexpr (!W4) halo_prologue();
     // rm, r0, rp, rn: f^n rows y-1, y, y+1, y+2 (prefetched);
     // q2, q1, qn: f^{n+1} rows y-2, y-1, y (qn computed here).  Health is
     // accumulated per lane and reported once per item (FP64 collision;
@@ -793,10 +799,10 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
         // register sets those rows rotate into: f^{n+1} of rows y1 - 1 and
         // y1 (the wrapped rows y0 - 1 and y0, computed first) and f^n of
         // rows y0 + 2 and y0 + 3 (the wrapped rows y0 - 2 and y0 - 1, loaded
-        // first).  Such a band loads each f^n row once and computes each
-        // f^{n+1} row once.
+        // first).  Such a band loads each f^n row once, all four before the
+        // march, and computes each f^{n+1} row once.
         const bool fresh = !(wrap4 && y >= y1 - 1);
-        if (more && !(wrap4 && y >= y0)) {
+        if (more && !wrap4) {
             unsigned long long a = row_at(fib, roff2(y + 2));
             const unsigned bo = lane_off(bcx);
 #pragma unroll
@@ -883,15 +889,17 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
 
     S A[16], B[16], Cw[16], D[16], E[16], F[16], G[16], H[16];
     {
-        const unsigned om = roff2(y0 - 2), o0 = roff2(y0 - 1), op = roff2(y0);
+        const unsigned om = roff2(y0 - 2), o0 = roff2(y0 - 1), op = roff2(y0), on = roff2(y0 + 1);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             A[i] = (moves_y(i) || wrap4) ? ld(i, om, cx) : S(0);
             B[i] = ld(i, o0, cx);
             Cw[i] = ld(i, op, cx);
-            D[i] = E[i] = F[i] = G[i] = H[i] = S(0);
+            D[i] = wrap4 ? ld(i, on, cx) : S(0);
+            E[i] = F[i] = G[i] = H[i] = S(0);
         }
     }
+    if constexpr (W4) halo_prologue();
     publish(B, (y0 - 1) & 1, 0);
     __syncthreads();
     // four register sets per level rotate, so no copies between rows
@@ -1052,8 +1060,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const Inst* __restrict__ i
 // ds[k] += sum over the n partial rows of partial[row][k]: one block of
 // 1024 threads, thread t sums column t % 16 over rows t / 16, t / 16 + 64,
 // ...; the 64 stripe sums are then added pairwise in six stages (a fixed
-// order, so the result is bitwise reproducible; the serial sum of the 64
-// took ~2 us of a 256^2 adjoint step).
+// order, so the result is bitwise reproducible).  A separate launch: having
+// the adjoint kernel's last block reduce instead (every block releasing its
+// rows device-wide) measured 2.2x slower at 256^2, the release fences
+// writing back the L2.
 constexpr int kReduceThreads = 1024;
 __global__ __launch_bounds__(kReduceThreads) void reduce_partials(const double* __restrict__ partial,
                                                                   int n, double* __restrict__ ds) {
@@ -1064,14 +1074,15 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_partials(const double* 
     for (int i = stripe; i < n; i += kStripes) v += partial[(long long)i * 16 + k];
     red[stripe][k] = v;
     __syncthreads();
-    // the stripe sums added pairwise, in a fixed order (a stage writes only
-    // the stripes below `half` and reads only those from `half` on)
+    // a stage writes only the stripes below `half` and reads only those from
+    // `half` on
     for (int half = kStripes / 2; half >= 1; half >>= 1) {
         if (stripe < half) red[stripe][k] += red[stripe + half][k];
         __syncthreads();
     }
     if (t < 16) ds[t] += red[0][t];
 }
+
 
 // ------------------------------------------------- scheme variants
 //

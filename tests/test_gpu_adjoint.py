@@ -191,3 +191,40 @@ def _unpadded_t(solver, buf):
     idx = (np.arange(16)[:, None, None] * solver.plane + solver.origin
            + np.arange(solver.ny)[None, :, None] * solver.pitch + np.arange(solver.nx)[None, None, :])
     return buf.view(solver.storage_dtype)[torch.as_tensor(idx.ravel(), device="cuda")]
+
+
+@pytest.mark.parametrize("n", [24, 512])
+def test_rate_gradient_reduction_repeats_bit_for_bit(n):
+    """The rate gradient of an adjoint step is reduced in a fixed order: ten
+    launches on the same input give the same ds bit for bit, on a grid of 24
+    adjoint blocks and on one of 1,024, and a launch accumulates onto what
+    ds holds."""
+    rho, T, s, dt, dx, dy = _small_case(n, n, seed=4)
+    sv = Solver(n, n, "fp32_eq64")
+    sv.set_params(1.4, s, dt, dx, dy)
+    r0, T0 = torch.tensor(rho, device="cuda"), torch.tensor(T, device="cuda")
+    zero = torch.zeros_like(r0)
+    # five steps off the initial equilibrium (at equilibrium the non-conserved
+    # moments equal theirs and the rate gradient vanishes)
+    f, g = sv.empty_state(), sv.empty_state()
+    sv.init_buffer(r0, zero, zero, T0, f)
+    for _ in range(5):
+        sv.step_buffers(f, g)
+        f, g = g, f
+    lam = _padded(sv, np.random.default_rng(5).standard_normal((16, n, n)))
+    out = sv.empty_state()
+    first = None
+    for rep in range(10):
+        ds = torch.zeros(16, dtype=torch.float64, device="cuda")
+        sv.adjoint_step(lam, f, out, ds)
+        torch.cuda.synchronize()
+        if first is None:
+            first = ds.clone()
+            print("ds", first.tolist(), flush=True)
+            assert torch.count_nonzero(first[4:]) >= 8 and torch.count_nonzero(first[:4]) == 0
+        assert torch.equal(ds, first), (rep, ds, first)
+    ds = first.clone()
+    sv.adjoint_step(lam, f, out, ds)
+    torch.cuda.synchronize()
+    assert torch.allclose(ds, 2 * first, rtol=1e-14, atol=0), (ds, first)
+    sv.close()
