@@ -1059,8 +1059,10 @@ __global__ __launch_bounds__(256) void adjoint_kernel(const Inst* __restrict__ i
 
 // ds[k] += sum over the n partial rows of partial[row][k]: one block of
 // 1024 threads, thread t sums column t % 16 over rows t / 16, t / 16 + 64,
-// ...; the 64 stripe sums are then added pairwise in six stages (a fixed
-// order, so the result is bitwise reproducible).  A separate launch: having
+// ... (eight at a time into eight sums: the serial chain of dependent loads
+// took 1.6 us of a 256^2 adjoint step); the 64 stripe sums are then added
+// pairwise in six stages (a fixed order, so the result is bitwise
+// reproducible).  A separate launch: having
 // the adjoint kernel's last block reduce instead (every block releasing its
 // rows device-wide) measured 2.2x slower at 256^2, the release fences
 // writing back the L2.
@@ -1070,9 +1072,19 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_partials(const double* 
     constexpr int kStripes = kReduceThreads / 16;
     __shared__ double red[kStripes][16];
     const int t = threadIdx.x, k = t & 15, stripe = t >> 4;
-    double v = 0.0;
-    for (int i = stripe; i < n; i += kStripes) v += partial[(long long)i * 16 + k];
-    red[stripe][k] = v;
+    // eight accumulators over the stripe's rows i, i + 64, ..., i + 448 of
+    // each group (eight loads in flight instead of a chain of dependent
+    // ones), added in a fixed order
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int i = stripe;
+    for (; i + 7 * kStripes < n; i += 8 * kStripes) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] += partial[(long long)(i + j * kStripes) * 16 + k];
+    }
+#pragma unroll
+    for (int j = 0; j < 7; ++j)      // fewer than eight rows left
+        if (i + j * kStripes < n) a[j] += partial[(long long)(i + j * kStripes) * 16 + k];
+    red[stripe][k] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     __syncthreads();
     // a stage writes only the stripes below `half` and reads only those from
     // `half` on
