@@ -36,15 +36,15 @@ HEADLINE_TILE_ROWS = 8              # the one-step kernel's band height for this
 # dispatch, mean over the step dispatches) of
 #   bench.py --steps 10 --warmup 2 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,315.3 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,315.6 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this band height; otherwise the roofline
 # reports traffic = null (comments are not hashed).
 MEASURED_TRAFFIC = {
-    "digest": "c72111a8496b2838811ccaebc36eebcccac25afdd646570438f26e7b86d100ab",
+    "digest": "7a8927ed4e602c980293ce8e00f6a7b20fc31518d4c61ed9b3755437a13613c3",
     "band_rows": HEADLINE_BAND_ROWS,
-    "fetch_kib": 770152.0, "fetch_copy_kib": 524315.3,
-    "write_kib": 1048581.9, "write_copy_kib": 1048576.0,
+    "fetch_kib": 769825.4, "fetch_copy_kib": 524315.6,
+    "write_kib": 1048576.4, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_internal.h")
 

@@ -80,11 +80,15 @@ __device__ __forceinline__ void no_value(S (&h)[16]) {
 constexpr bool moves_x(int i) { return i < 8 ? (i & 1) == 0 : true; }
 constexpr bool moves_y(int i) { return i < 8 ? (i & 1) == 1 : true; }
 
-// Conserved moments as compensated (Neumaier) FP32 sums over the 16
-// populations: rho = sum f, j = sum v f, e = sum (v^2 + eta^2) f.
+// Conserved moments as compensated FP32 sums over the 16 populations:
+// rho = sum f, j = sum v f, e = sum (v^2 + eta^2) f.  Each addition's
+// rounding error is recovered exactly by Knuth's branch-free TwoSum (the same
+// error Neumaier's ordered form recovers, without its compare and select)
+// and accumulated in c.
 __device__ __forceinline__ void neumaier(float& s, float& c, float x) {
     const float t = s + x;
-    c += (fabsf(s) >= fabsf(x)) ? ((s - t) + x) : ((x - t) + s);
+    const float bp = t - s, ap = t - bp;
+    c += (s - ap) + (x - bp);
     s = t;
 }
 __device__ __forceinline__ void conserved_compensated(const float f[16], float q[4]) {
