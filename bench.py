@@ -296,8 +296,23 @@ def roofline(case, precision, r, traffic=None):
     return out
 
 
-def cpu_baseline(rows=512, steps=2):
-    """The FP64 oracle on a band of the headline workload (4096 x rows)."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_band(rows, steps, start_barrier=None, out=None):
+    """The FP64 oracle (one BLAS thread) on a 4096 x rows band of the
+    headline workload: `steps` steps after setup; returns (cells x steps,
+    start, end) in wall-clock seconds.  With a barrier every worker starts
+    its timed steps together."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -309,14 +324,51 @@ def cpu_baseline(rows=512, steps=2):
                    bc=[bcmap[b] for b in case.bc], side_state=case.side_state)
     with threadpool_limits(limits=1):
         f = mrt.init_populations(case.rho, case.ux, case.uy, case.T, p)
-        t0 = time.perf_counter()
+        if start_barrier is not None:
+            start_barrier.wait()
+        t0 = time.time()
         for _ in range(steps):
             f = mrt.step(f, p)
-        sec = time.perf_counter() - t0
+        t1 = time.time()
     assert np.isfinite(f).all()
-    return {"value": round(case.cells * steps / sec / 1e6, 4), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} steps of a 4096x{rows} band of the shock-bubble case (FP64 NumPy oracle, 1 thread)"}
+    res = (case.cells * steps, t0, t1)
+    if out is not None:
+        out.put(res)
+    return res
+
+
+def cpu_baseline(rows1=1024, steps1=6, rows_all=256, steps_all=6, max_workers=16):
+    """The FP64 NumPy oracle on the host cores, as it stands: one process on
+    a 4096 x rows1 band, then one process per core (capped at the CPU share
+    a one-GPU host gives a job, max_workers) each on its own 4096 x rows_all
+    band, started together; MLUPS = site updates / wall time."""
+    import multiprocessing as mp
+    n1, t0, t1 = _oracle_band(rows1, steps1)
+    v1 = n1 / (t1 - t0) / 1e6
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(max_workers, avail))
+    ctx = mp.get_context("spawn")        # fresh interpreters: no GPU state inherited
+    bar = ctx.Barrier(workers)
+    q = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_band, args=(rows_all, steps_all, bar, q)) for _ in range(workers)]
+    for pr in procs:
+        pr.start()
+    res = [q.get(timeout=600) for _ in procs]
+    for pr in procs:
+        pr.join()
+    total = sum(r[0] for r in res)
+    wall = max(r[2] for r in res) - min(r[1] for r in res)
+    vall = total / wall / 1e6
+    return {"value": round(vall, 4), "unit": "MLUPS", "cores": workers, "kind": "oracle",
+            "value_1core": round(v1, 4), "value_allcore": round(vall, 4),
+            "nproc": os.cpu_count(), "cores_available": avail, "cpu_model": _cpu_model(),
+            "sample": (f"FP64 NumPy oracle (one BLAS thread per process) on bands of the 4096^2 "
+                       f"shock-bubble case: 1 core {steps1} steps of 4096x{rows1}; all cores "
+                       f"{workers} processes x {steps_all} steps of 4096x{rows_all} each, "
+                       f"started together")}
 
 
 def main():

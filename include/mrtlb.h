@@ -134,15 +134,16 @@ int mrt_set_fields(mrt_ctx* ctx, const double* rho, const double* ux, const doub
  * Errors: MRT_ESTATE, MRT_EINVAL (n < 0). */
 int mrt_step(mrt_ctx* ctx, int n);
 
-/* Capture (without running anything) the HIP graphs that a following
- * mrt_step(ctx, n) will replay, so that their one-time capture and
- * instantiation cost (about a millisecond for 64 passes) falls outside a timed
- * region or a latency-critical loop.  The kernel passes of mrt_step(n) (n, or
- * n / 2 with two steps per pass) are replayed as replays of one 64-pass graph
- * and one graph of the remaining passes, per start buffer (an odd step of the
- * two-step mode is launched directly); the graphs are kept until the tile,
- * steps per pass, scheme or context changes.  Runs nothing on the GPU; errors
- * as mrt_step. */
+/* Capture, instantiate and upload (without running any kernel) the HIP
+ * graphs that a following mrt_step(ctx, n) will replay, so that their
+ * one-time capture, instantiation and upload cost (about a millisecond for
+ * 64 passes) falls outside a timed region or a latency-critical loop.  The
+ * kernel passes of mrt_step(n) (n, or n / 2 with two steps per pass) are
+ * replayed as replays of one 64-pass graph and one graph of the remaining
+ * passes, per start buffer (an odd step of the two-step mode is launched
+ * directly); the graphs are kept until the tile, steps per pass, scheme or
+ * context changes.  Launches no kernel (the uploads are enqueued on the
+ * context's stream); errors as mrt_step. */
 int mrt_prepare_steps(mrt_ctx* ctx, int n);
 
 /* Macroscopic fields of the current populations: rho = fhat_1, u = j/rho,

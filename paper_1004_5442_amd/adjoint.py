@@ -44,6 +44,9 @@ class DensityMap(torch.autograd.Function):
         rhoN = torch.empty_like(rho0d)
         solver.density(a, rhoN)
         ctx.solver, ctx.K, ctx.nsteps = solver, K, nsteps
+        # the parameters this forward ran with: the solver may be given other
+        # ones (another forward, a finite-difference loop) before backward
+        ctx.params = (gamma, sv.tolist(), dt, dx, dy)
         ctx.checkpoints = checkpoints
         ctx.save_for_backward(rho0d, T0d)
         ctx.s_meta = (s.device, s.dtype)
@@ -53,6 +56,8 @@ class DensityMap(torch.autograd.Function):
     def backward(ctx, g_rhoN: torch.Tensor):
         solver, K, N = ctx.solver, ctx.K, ctx.nsteps
         rho0d, T0d = ctx.saved_tensors
+        gamma, s_list, dt, dx, dy = ctx.params
+        solver.set_params(gamma, s_list, dt, dx, dy, 0.0)
         lam, lam2 = solver.empty_state(), solver.empty_state()
         solver.density_adjoint(g_rhoN.detach().to(torch.float64).contiguous(), lam)
         ds = torch.zeros(16, dtype=torch.float64, device=rho0d.device)

@@ -93,3 +93,18 @@ def fp64_rounding_spread(case, nsteps, want, seed=0):
         f = mrt.step(f, p)
         f = f * (1.0 + np.ldexp(rng.choice([-1.0, 1.0], size=f.shape), -52))
     return float(np.max(np.abs(f - want)) / np.abs(want).max())
+
+
+def one_row(case):
+    """The same case on a single periodic row: for a case that is uniform in
+    y with periodic y sides (the shock tubes) every row of the oracle does
+    the same arithmetic on the same values, and the y increments of a
+    uniform column are exactly zero, so the one-row oracle run gives the
+    rows of the full one bit for bit at a fraction of the cost (checked by
+    tests/test_workloads.py)."""
+    import dataclasses
+    assert case.bc[2] == case.bc[3] == "periodic"
+    for a in (case.rho, case.ux, case.uy, case.T):
+        assert np.all(a == a[:1]), "the case is not uniform in y"
+    return dataclasses.replace(case, ny=1, rho=case.rho[:1].copy(), ux=case.ux[:1].copy(),
+                               uy=case.uy[:1].copy(), T=case.T[:1].copy())

@@ -228,3 +228,64 @@ def test_rate_gradient_reduction_repeats_bit_for_bit(n):
     torch.cuda.synchronize()
     assert torch.allclose(ds, 2 * first, rtol=1e-14, atol=0), (ds, first)
     sv.close()
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32_eq64", 1e-6)])
+def test_init_adjoint_all_four_gradients_match_oracle(precision, tol):
+    """mrt_init_adjoint's g_rho, g_ux, g_uy and g_T against the oracle's
+    init_adjoint (complex step of init_populations) on a moving state whose
+    two velocity components differ, so that a swapped or mis-indexed
+    velocity gradient fails.  FP64 at 1e-12 of each gradient's scale; FP32
+    storage only rounds lam0 on the way in (the Jacobian is FP64 there)."""
+    rng = np.random.default_rng(21)
+    ny, nx = 11, 67
+    rho = 1 + 0.1 * rng.standard_normal((ny, nx))
+    T = 1 + 0.1 * rng.standard_normal((ny, nx))
+    ux = 0.3 + 0.2 * rng.standard_normal((ny, nx))
+    uy = -0.2 + 0.2 * rng.standard_normal((ny, nx))
+    s = W.rates(5e3, 1e4, 0.71, 1e4)
+    p = mrt.Params(gamma=1.4, s=s, dt=1e-4, dx=1.0 / nx, dy=1.0 / ny)
+    lam0 = rng.standard_normal((16, ny, nx))
+    sv = Solver(nx, ny, precision)
+    sv.set_params(1.4, s, 1e-4, 1.0 / nx, 1.0 / ny)
+    lam_d = _padded(sv, lam0)
+    # the oracle sees lam0 as the device stores it
+    lam_used = _unpadded(sv, lam_d)
+    want = oadj.init_adjoint(lam_used, rho, ux, uy, T, p)
+    dev = [torch.tensor(a, device="cuda") for a in (rho, ux, uy, T)]
+    outs = [torch.full((ny, nx), np.nan, dtype=torch.float64, device="cuda") for _ in range(4)]
+    sv.init_adjoint(lam_d, *dev, g_rho=outs[0], g_ux=outs[1], g_uy=outs[2], g_T=outs[3])
+    torch.cuda.synchronize()
+    for k, name in enumerate(("rho", "ux", "uy", "T")):
+        got = outs[k].cpu().numpy()
+        err = np.max(np.abs(got - want[k])) / np.max(np.abs(want[k]))
+        print(precision, name, "relative error", err, flush=True)
+        assert err <= tol, (name, err)
+    sv.close()
+
+
+def test_backward_uses_the_parameters_of_its_own_forward():
+    """Two forwards with different rates on one solver, then backward of the
+    first: the gradient is that of the first forward's parameters (the
+    adjoint sweep re-applies them), equal bit for bit to a run without the
+    second forward."""
+    rho, T, s, dt, dx, dy = _small_case(32, 16, seed=9)
+    sv = Solver(32, 16, "fp64")
+    s2 = np.array(s) * 0.5
+
+    def grad(with_second):
+        r0 = torch.tensor(rho, device="cuda", requires_grad=True)
+        rhoN = density_after(r0, torch.tensor(T, device="cuda"), torch.tensor(s, device="cuda"),
+                             sv, 1.4, dt, dx, dy, 12, segment=4)
+        if with_second:
+            with torch.no_grad():
+                density_after(r0.detach(), torch.tensor(T, device="cuda"),
+                              torch.tensor(s2, device="cuda"), sv, 1.4, dt, dx, dy, 12, segment=4)
+        (rhoN ** 2).sum().backward()
+        torch.cuda.synchronize()
+        return r0.grad.cpu().numpy()
+
+    a = grad(False)
+    b = grad(True)
+    assert np.array_equal(a, b)
+    sv.close()

@@ -4,7 +4,8 @@ each against its own oracle run."""
 import numpy as np
 import pytest
 
-from helpers import field_errors, fp32_tolerances, oracle_params, oracle_run, smooth_case
+from helpers import (field_errors, fp32_tolerances, one_row, oracle_params, oracle_run,
+                     smooth_case)
 from oracle import mrt
 from paper_1004_5442_amd import workloads as W
 
@@ -130,20 +131,49 @@ def test_batch_autotune_after_two_step_passes():
         assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
 
 
-def test_full_batch_512_tubes_sampled():
-    """The full batched workload (512 tubes, 1000 steps, FP32 + FP64
-    collision) in its autotuned launch; the three shortest tubes are
-    compared with the oracle."""
-    cases = W.tube_batch(512, seed=0)
-    b = Batch(cases, "fp32_eq64")
-    b.autotune(4)
-    print("autotuned", b.tile(), b.steps_per_pass(), flush=True)
-    b.step(1000)
-    order = np.argsort([c.nx for c in cases])[:3]
-    for i in order:
-        c = cases[i]
-        want, p = oracle_run(c, 1000)
-        err = field_errors(b.moments(int(i)), mrt.macroscopic(want, p.b))
-        tol = fp32_tolerances(c, 1000, want)
-        print(c.name, c.nx, err, tol, flush=True)
-        assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+# The full batched workload's tubes compared with the oracle, chosen by the
+# parameters that stress FP32 storage: the largest pressure ratio (shock
+# Mach ~5, lowest right density), both gamma extremes, both Prandtl-number
+# extremes and the longest tube (selected from the seed, not by cost).
+_FULL = {}
+
+
+def _full_batch():
+    if not _FULL:
+        cases = W.tube_batch(512, seed=0)
+        b = Batch(cases, "fp32_eq64")
+        b.autotune(4)
+        print("autotuned", b.tile(), b.steps_per_pass(), flush=True)
+        b.step(1000)
+        r = [c.meta["pressure_ratio"] for c in cases]
+        g = [c.gamma for c in cases]
+        pr = [c.Pr for c in cases]
+        sel = {"max_pressure_ratio": int(np.argmax(r)), "min_gamma": int(np.argmin(g)),
+               "max_gamma": int(np.argmax(g)), "min_Pr": int(np.argmin(pr)),
+               "max_Pr": int(np.argmax(pr)), "longest": int(np.argmax([c.nx for c in cases]))}
+        _FULL["cases"] = cases
+        _FULL["sel"] = sel
+        _FULL["moments"] = {i: b.moments(i) for i in set(sel.values())}
+        b.close()
+    return _FULL
+
+
+@pytest.mark.parametrize("which", ["max_pressure_ratio", "min_gamma", "max_gamma", "min_Pr",
+                                   "max_Pr", "longest"])
+def test_full_batch_512_tubes_hardest(which):
+    """512 tubes, 1000 steps, FP32 storage with FP64 collision, in the
+    batch's autotuned launch; the selected tube's rho, u, T against the FP64
+    oracle (run on one row: the tubes are uniform and periodic in y).  The
+    bound is the stated 1e-5 or twice what FP32 storage alone costs on this
+    tube, whichever is larger; both numbers are printed."""
+    full = _full_batch()
+    i = full["sel"][which]
+    c = full["cases"][i]
+    c1 = one_row(c)
+    want, p = oracle_run(c1, 1000)
+    got = [a[:1] for a in full["moments"][i]]
+    err = field_errors(got, mrt.macroscopic(want, p.b))
+    tol = fp32_tolerances(c1, 1000, want)
+    print(which, c.name, f"nx {c.nx} gamma {c.gamma:.3f} Pr {c.Pr:.3f} "
+          f"r {c.meta['pressure_ratio']:.1f}", "err", err, "tol", tol, flush=True)
+    assert all(err[k] < tol[k] for k in err), (c.name, err, tol)

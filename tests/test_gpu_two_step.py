@@ -285,3 +285,32 @@ def test_two_step_conserves_mass_momentum_energy_at_full_size():
                                      storage_offset=r.origin).clone())
         r.close()
     assert torch.equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp32"])
+def test_plain_launches_equal_graph_replays(precision):
+    """Two steps per pass: step(2) called four times launches the two-step
+    kernel directly each time (the path the autotuner times), step(8)
+    replays one captured graph of four passes; both must run every pass and
+    give the same populations bit for bit, and an odd count (step(3) = one
+    two-step pass and one single step) matches step(2) + step(1)."""
+    case = smooth_case(300, 40, ("eq", "outflow", "reflect", "reflect"), seed=17)
+    a = solver_for_case(case, precision)
+    b = solver_for_case(case, precision)
+    for s in (a, b):
+        s.set_steps_per_pass(2, 8)
+    for _ in range(4):
+        a.step(2)
+    b.step(8)
+    fa, fb = a.populations(), b.populations()
+    assert np.array_equal(fa, fb)
+    a.step(3)
+    b.step(2)
+    b.step(1)
+    assert np.array_equal(a.populations(), b.populations())
+    # and eight steps really ran: the oracle after 11 steps
+    want, p = oracle_run(case, 11)
+    err = field_errors(a.moments(), mrt.macroscopic(want, p.b))
+    assert all(v < 1e-5 for v in err.values()), err
+    a.close()
+    b.close()

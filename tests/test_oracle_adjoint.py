@@ -90,3 +90,30 @@ def test_loss_gradient_matches_central_differences():
         ad = np.sum(g["rho"] * dr) + np.sum(g["T"] * dT) + np.sum(g["s"] * ds)
         assert ad == pytest.approx(fd, rel=1e-6)
     assert np.max(np.abs(g["s"][:4])) <= 1e-12 * np.max(np.abs(g["s"]))
+
+
+def test_init_adjoint_all_four_fields_against_central_differences():
+    """Every output of init_adjoint, the velocity gradients included, against
+    central differences of <lam0, f^0> taken cell by cell from the real-valued
+    init_populations: f^0 is local, so moving one field by eps in every cell
+    at once changes each cell's own term only.  The fields have distinct,
+    non-zero velocities in both directions, so swapped or sign-flipped ux / uy
+    gradients fail."""
+    ny, nx = 5, 7
+    p = _params(nx, ny)
+    rho, ux, uy, T = _fields(ny, nx, 7)
+    ux = ux + 0.3
+    uy = uy - 0.2
+    lam0 = RNG.standard_normal((16, ny, nx))
+    got = adjoint.init_adjoint(lam0, rho, ux, uy, T, p)
+    fields = [rho, ux, uy, T]
+    for k, name in enumerate(("rho", "ux", "uy", "T")):
+        eps = 1e-6 * max(1.0, float(np.max(np.abs(fields[k]))))
+        up = [a.copy() for a in fields]
+        dn = [a.copy() for a in fields]
+        up[k] = up[k] + eps
+        dn[k] = dn[k] - eps
+        fd = np.sum(lam0 * (mrt.init_populations(*up, p) - mrt.init_populations(*dn, p)), axis=0) / (2 * eps)
+        assert np.max(np.abs(got[k] - fd)) <= 1e-7 * np.max(np.abs(fd)), name
+    # the two velocity gradients are different functions of the state
+    assert np.max(np.abs(got[1] - got[2])) > 0.1 * np.max(np.abs(got[1]))

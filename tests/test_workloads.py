@@ -132,3 +132,15 @@ def test_strong_shock_tube_states_and_rates():
     xc = (np.arange(m.nx) + 0.5) * m.dx
     assert np.all(m.rho[0][xc < x0] == L[0]) and np.all(m.rho[0][xc > x0] == R[0])
     assert m.bc == ("eq", "eq", "periodic", "periodic")
+
+
+def test_one_row_oracle_equals_full_tube_oracle():
+    """The shock tubes are uniform in y and periodic in y: the oracle on one
+    row reproduces every row of the four-row oracle bit for bit (the batch
+    parity test relies on this to run the long tubes' oracle cheaply)."""
+    from helpers import one_row, oracle_run
+    c = W.tube_batch(3, seed=5, nx_range=(60, 90), nsteps=60)[2]
+    full, _ = oracle_run(c, 60)
+    row, _ = oracle_run(one_row(c), 60)
+    for j in range(c.ny):
+        assert np.array_equal(full[:, j], row[:, 0])
