@@ -29,7 +29,7 @@ hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool r
                      const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
                      const void* fn, void* lout, double* partial, bool accumulate, double* ds,
-                     hipStream_t st);
+                     bool nt, hipStream_t st);
 hipError_t k_init(int prec, const Inst* P, long long cells, const double* rho, const double* ux,
                   const double* uy, const double* T, void* f, hipStream_t st);
 hipError_t k_moments(int prec, const Inst* P, long long cells, const void* f, double* rho,
@@ -305,7 +305,7 @@ struct mrt_ctx {
     bool eager = false;              // launch step by step (the tile autotuner)
     int scheme = 0;                  // MRT_SCHEME_* flags
     void* f_tmp = nullptr;           // post-collision state of the split scheme
-    Item* d_items_adj = nullptr;     // work items of the adjoint kernel (finer bands)
+    Item* d_items_adj = nullptr;     // work items of the adjoint kernel
     int nitems_adj = 0;
     double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
     double* d_partial = nullptr;     // 16 doubles per wave of an adjoint item: partial sums
@@ -374,16 +374,21 @@ int build_items2(mrt_ctx* c, int rows) {
     return MRT_OK;
 }
 
-// Work items of the adjoint kernel.  It keeps no register window across rows
-// (each row loads its own neighbours), so its bands are as short as it takes
-// to give ~1024 blocks (4096 waves), down to one row: a small grid then still
-// spreads over the whole chip.
+// Work items of the adjoint kernel: 256-column chunks of row bands, marched
+// like the one-step kernel's.  Bands of up to 16 rows while the grid still
+// gives ~2048 items (four blocks per block slot of the chip at two 4-wave
+// blocks per CU), down to one row on small grids so that they still spread
+// over the chip.
+int adjoint_rows(int nx, int ny) {
+    const long long chunks = (nx + 255) / 256;
+    const long long r = std::max<long long>(1, std::min<long long>(16, chunks * ny / 2048));
+    return int(std::min<long long>(r, ny));
+}
+
 int build_adjoint_items(mrt_ctx* c) {
     std::string& ctx_err = c->err;
-    const long long chunks = (c->nx + 255) / 256;
-    const int rows = int(std::max<long long>(1, std::min<long long>(64, (chunks * c->ny + 1023) / 1024)));
     std::vector<Item> items;
-    add_items(items, 0, c->nx, c->ny, std::min(rows, c->ny));
+    add_items(items, 0, c->nx, c->ny, adjoint_rows(c->nx, c->ny));
     HIPTRY(hipMalloc(&c->d_items_adj, items.size() * sizeof(Item)));
     HIPTRY(hipMemcpy(c->d_items_adj, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
     HIPTRY(hipMalloc(&c->d_partial, items.size() * 4 * 16 * sizeof(double)));
@@ -905,7 +910,7 @@ int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* la
     if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
         return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
     HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, lam_next, f_n, lam_n,
-                          c->d_partial, false, ds, c->stream));
+                          c->d_partial, false, ds, c->nt, c->stream));
     return MRT_OK;
 }
 
@@ -967,7 +972,7 @@ int mrt_adjoint_sweep(mrt_ctx* c, const void* const* checkpoints, int segment, i
         for (int n = stop - 1; n >= start; --n) {
             HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, cur,
                                   state(n - start), nxt, c->d_partial, !first,
-                                  n == 0 ? ds : nullptr, c->stream));
+                                  n == 0 ? ds : nullptr, c->nt, c->stream));
             first = false;
             std::swap(cur, nxt);
         }
@@ -1452,7 +1457,8 @@ int mrt_host_cell_adjoint(double gamma, const double* s, double dt, const double
     if (!s || !f || !lam || !coll || !dsk || !(gamma > 1.0)) return MRT_EINVAL;
     double sdt[16];
     for (int k = 0; k < 16; ++k) sdt[k] = k < 4 ? 0.0 : s[k] * dt;
-    mrt::cell_adjoint<double>(f, lam, 2.0 / (gamma - 1.0), sdt, dt, coll, dsk);
+    const double b = 2.0 / (gamma - 1.0);
+    mrt::cell_adjoint<double>(f, lam, b, 1.0 / b, sdt, dt, coll, dsk);
     return MRT_OK;
 }
 

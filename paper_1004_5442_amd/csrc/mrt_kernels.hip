@@ -948,83 +948,140 @@ __global__ __launch_bounds__(256, 2) void step2_kernel(const Inst* __restrict__ 
 // Adjoint of one step on a periodic grid (neighbours wrap through the
 // boundary remap of Inst), per cell x (lam = lam^{n+1}):
 //   lam^n(x) = lam(x) + LW^T(lam)(x) - dt (dC/df(x))^T lam(x)
-// with the collision part from cell_adjoint (mrt_dual.h).  Partial sums of
-// the rate gradient per wave go to `partial` (16 doubles per wave; with
-// `accumulate` they are added to what the row holds, so a sweep of many
-// steps is reduced once), reduced in a fixed order by reduce_partials.
-template <typename S, typename C>
-__device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int item, int x0, int y0,
-                                             int y1, const S* __restrict__ lin,
-                                             const S* __restrict__ fn, S* __restrict__ lout,
-                                             double* __restrict__ partial, bool accumulate) {
+// with the collision part from cell_adjoint (mrt_dual.h).  LW^T is the
+// forward stencil with mirrored neighbours: the weight f(x+1) had in F(x)
+// now multiplies lam(x-1) and vice versa, so lam^n is site_update with the
+// W / E and So / N arguments swapped and dt (dC/df)^T lam in place of dt C.
+//
+// A work item is a block of four waves over 256 columns of a band of rows,
+// marching up the band as step_block does: lam rows y-1 .. y+2 in a register
+// window of four rotating sets (row y + 2 prefetched), f^n of row y and y + 1
+// in two alternating sets (f^n is read at the cell only), x neighbours by
+// DPP lane shifts, the edge lanes' values through LDS and the two halo
+// columns by a load on one lane each.  Each of lam^{n+1}, f^n and lam^n then
+// crosses the memory interface once per cell (plus the band's two halo rows
+// of lam), 192 B per cell in FP32 storage.  Partial sums of the rate
+// gradient per wave go to `partial` (16 doubles per wave; with `accumulate`
+// they are added to what the row holds, so a sweep of many steps is reduced
+// once), reduced in a fixed order by reduce_partials.
+template <typename S, typename C, bool NT>
+__device__ __forceinline__ void adjoint_block(const Inst* __restrict__ P, int item, int x0, int y0,
+                                              int y1, const S* __restrict__ lin,
+                                              const S* __restrict__ fn, S* __restrict__ lout,
+                                              double* __restrict__ partial, bool accumulate,
+                                              EdgeBuf<S>& lds) {
     const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const long long plane = P->plane;
     const S* __restrict__ li = lin + P->off;
     const S* __restrict__ fi = fn + P->off;
     S* __restrict__ lo = lout + P->off;
     const int nx = P->nx;
-    const int x = x0 + lane;
+    const int x = x0 + 64 * wv + lane;
     const bool act = x < nx;
+    // load column (lanes past the grid read the wrapped neighbour) and store
+    // column (lanes past the grid write the unread column nx + 1)
     const unsigned cx = unsigned(act ? x : P->col_hi);
     const unsigned xs = unsigned(act ? x : nx + 1);
-    const C b = C(P->b);
-    unsigned hx = cx;
-    if (lane == 0) hx = unsigned(x0 > 0 ? x0 - 1 : P->col_lo);
-    if (lane == 63) hx = unsigned(x0 + 64 < nx ? x0 + 64 : P->col_hi);
-    const bool hload = (lane == 0 || lane == 63);
-    // row + col summed in 32 bits, as in the step kernel
+    const C b = C(P->b), binv = C(P->binv), dt = C(P->dt);
     auto ldl = [&](int i, unsigned row, unsigned col) -> S { return (li + (long long)i * plane)[row + col]; };
     auto ldf = [&](int i, unsigned row, unsigned col) -> S { return (fi + (long long)i * plane)[row + col]; };
+    const bool hmem = (wv == 0 && lane == 0) || (wv == kWaves - 1 && lane == 63);
+    unsigned hx = cx;
+    if (wv == 0 && lane == 0) hx = unsigned(x0 > 0 ? x0 - 1 : P->col_lo);
+    if (wv == kWaves - 1 && lane == 63) hx = unsigned(x0 + 256 < nx ? x0 + 256 : P->col_hi);
+    const bool edge_lane = lane == 0 || lane == 63;
+    const int eside = lane == 0 ? 0 : 1;
+    const int nwave = lane == 0 ? wv - 1 : wv + 1;
+    const int nside = lane == 0 ? 1 : 0;
+    const bool hlds = edge_lane && !hmem;
     double acc[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k) acc[k] = 0.0;
-    for (int y = y0; y < y1; ++y) {
-        const unsigned o = row_offset(P, y), om = row_offset(P, y - 1), op = row_offset(P, y + 1);
-        S l0[16], lm[16], lp[16], fc[16], h[16];
+
+    auto publish = [&](const S (&r)[16], int slot) {
+        if (edge_lane) {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            l0[i] = ldl(i, o, cx);
-            fc[i] = ldf(i, o, cx);
-            lm[i] = moves_y(i) ? ldl(i, om, cx) : S(0);
-            lp[i] = moves_y(i) ? ldl(i, op, cx) : S(0);
-            h[i] = S(0);
+            for (int i = 0; i < 16; ++i)
+                if (moves_x(i)) lds.v[slot][wv][eside][xslot(i)] = r[i];
         }
-        if (hload) {
+    };
+
+    // row y: lam window rm / r0 / rp (rows y-1, y, y+1), rn <- row y + 2;
+    // fc = f^n of row y, fnx <- f^n of row y + 1
+    auto body = [&](const S (&rm)[16], const S (&r0)[16], const S (&rp)[16], S (&rn)[16],
+                    const S (&fc)[16], S (&fnx)[16], int y) {
+        const bool more = y + 1 < y1;
+        if (more) {
+            const unsigned on = row_offset(P, y + 2), of = row_offset(P, y + 1);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) rn[i] = ldl(i, on, cx);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) fnx[i] = ldf(i, of, cx);
+        }
+        const unsigned o = row_offset(P, y);
+        S h[16];
+        no_value(h);
+        if (hmem) {
 #pragma unroll
             for (int i = 0; i < 16; ++i)
                 if (moves_x(i)) h[i] = ldl(i, o, hx);
+        } else if (hlds) {
+            const int slot = y & 1;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (moves_x(i)) h[i] = lds.v[slot][nwave][nside][xslot(i)];
         }
         C f[16], lam[16], coll[16], dsk[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             f[i] = C(fc[i]);
-            lam[i] = C(l0[i]);
+            lam[i] = C(r0[i]);
         }
-        cell_adjoint(f, lam, b, P->sdt, C(P->dt), coll, dsk);
+        cell_adjoint(f, lam, b, binv, P->sdt, dt, coll, dsk);
         if (act) {
 #pragma unroll
             for (int k = 4; k < 16; ++k) acc[k] -= double(dsk[k]);
         }
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int k = i >> 2, sx = sgn_x(i), sy = sgn_y(i);
-            S d = S(0);
-            // transpose of the forward stencil: the weight that f(x+1) had in
-            // F(x) now multiplies lam(x-1), and vice versa
-            if (sx != 0) {
-                const S W = from_left(l0[i], h[i]);
-                const S E = from_right(l0[i], h[i]);
-                const S wd = Weights<S>::get(P, 0, k, 0), wu = Weights<S>::get(P, 0, k, 1);
-                const S e = E - l0[i], w = W - l0[i];
-                d = sx > 0 ? (wd * w + wu * e) : (wu * w + wd * e);
-            }
-            if (sy != 0) {
-                const S wd = Weights<S>::get(P, 1, k, 0), wu = Weights<S>::get(P, 1, k, 1);
-                const S n = lp[i] - l0[i], s = lm[i] - l0[i];
-                d += sy > 0 ? (wd * s + wu * n) : (wu * s + wd * n);
-            }
-            (lo + (long long)i * plane)[o + xs] = l0[i] + (d - S(coll[i]));
+            const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
+            const S E = moves_x(i) ? from_right(r0[i], h[i]) : S(0);
+            S* dst = &(lo + (long long)i * plane)[o + xs];
+            // mirrored neighbours: (E, W) and (N, So) in the (W, E), (So, N) slots
+            const S v = site_update(P, i, r0[i], E, W, rp[i], rm[i], S(coll[i]));
+            if constexpr (NT)
+                __builtin_nontemporal_store(v, dst);
+            else
+                *dst = v;
         }
+        if (more) publish(rp, (y + 1) & 1);
+        __syncthreads();
+    };
+
+    S A[16], B[16], Cw[16], D[16], F0[16], F1[16];
+    {
+        const unsigned om = row_offset(P, y0 - 1), o0 = row_offset(P, y0), op = row_offset(P, y0 + 1);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            B[i] = ldl(i, o0, cx);
+            Cw[i] = ldl(i, op, cx);
+            A[i] = moves_y(i) ? ldl(i, om, cx) : S(0);
+            D[i] = S(0);
+            F0[i] = ldf(i, o0, cx);
+            F1[i] = S(0);
+        }
+    }
+    publish(B, y0 & 1);
+    __syncthreads();
+    for (int y = y0; y < y1;) {
+        body(A, B, Cw, D, F0, F1, y); ++y;
+        if (y >= y1) break;
+        body(B, Cw, D, A, F1, F0, y); ++y;
+        if (y >= y1) break;
+        body(Cw, D, A, B, F0, F1, y); ++y;
+        if (y >= y1) break;
+        body(D, A, B, Cw, F1, F0, y); ++y;
     }
     // wave reduction of the 12 non-trivial rate gradients
 #pragma unroll
@@ -1035,29 +1092,38 @@ __device__ __forceinline__ void adjoint_item(const Inst* __restrict__ P, int ite
         acc[k] = v;
     }
     if (lane == 0) {
+        double* row = &partial[((long long)item * kWaves + wv) * 16];
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
-            double* dst = &partial[(long long)item * 16 + k];
             const double v = k < 4 ? 0.0 : acc[k];
-            *dst = accumulate ? *dst + v : v;
+            row[k] = accumulate ? row[k] + v : v;
         }
     }
 }
 
-template <typename S, typename C>
-__global__ __launch_bounds__(256) void adjoint_kernel(const Inst* __restrict__ insts,
-                                                      const Item* __restrict__ items, int nitems,
-                                                      const S* __restrict__ lin,
-                                                      const S* __restrict__ fn,
-                                                      S* __restrict__ lout,
-                                                      double* __restrict__ partial,
-                                                      int accumulate) {
-    // one block per 256-column item; wave w takes columns x0 + 64 w
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    for (int w = blockIdx.x; w < nitems; w += gridDim.x) {
+// Two blocks per CU (two waves per SIMD, at most 256 VGPRs) for FP32
+// storage; FP64 storage holds twice the register window and runs one.
+template <typename S>
+constexpr int adjoint_waves() { return sizeof(S) == 4 ? 2 : 1; }
+
+template <typename S, typename C, bool NT>
+__global__ __launch_bounds__(256, (adjoint_waves<S>())) void adjoint_kernel(const Inst* __restrict__ insts,
+                                                         const Item* __restrict__ items, int nitems,
+                                                         const S* __restrict__ lin,
+                                                         const S* __restrict__ fn,
+                                                         S* __restrict__ lout,
+                                                         double* __restrict__ partial,
+                                                         int accumulate) {
+    __shared__ EdgeBuf<S> lds;
+    // XCD-aware item order as in step_kernel
+    const int per = (nitems + 7) >> 3;
+    for (int q = blockIdx.x; q < 8 * per; q += gridDim.x) {
+        const int w = (q & 7) * per + (q >> 3);
+        if (w >= nitems) continue;
         const Item it = items[w];
-        adjoint_item<S, C>(insts + it.inst, w * kWaves + wv, it.x0 + 64 * wv, it.y0, it.y1, lin,
-                           fn, lout, partial, accumulate != 0);
+        adjoint_block<S, C, NT>(insts + it.inst, w, it.x0, it.y0, it.y1, lin, fn, lout, partial,
+                                accumulate != 0, lds);
+        __syncthreads();   // the next item reuses the edge buffer
     }
 }
 
@@ -1452,32 +1518,32 @@ hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool r
     }
 }
 
-// One adjoint step; partial rows are overwritten (accumulate = false) or
-// added to (true); ds != NULL: then reduce the partial rows into ds.
+// One adjoint step; partial rows (kWaves per item) are overwritten
+// (accumulate = false) or added to (true); ds != NULL: then reduce the
+// partial rows into ds.  nt: non-temporal stores of lam^n.
+template <typename S, typename C>
+void launch_adjoint(const Inst* insts, const Item* items, int nitems, const void* lin,
+                    const void* fn, void* lout, double* partial, int acc, bool nt, hipStream_t st) {
+    const int blocks = 8 * ((nitems + 7) / 8);
+    if (nt)
+        hipLaunchKernelGGL((adjoint_kernel<S, C, true>), dim3(blocks), dim3(256), 0, st, insts, items,
+                           nitems, static_cast<const S*>(lin), static_cast<const S*>(fn),
+                           static_cast<S*>(lout), partial, acc);
+    else
+        hipLaunchKernelGGL((adjoint_kernel<S, C, false>), dim3(blocks), dim3(256), 0, st, insts, items,
+                           nitems, static_cast<const S*>(lin), static_cast<const S*>(fn),
+                           static_cast<S*>(lout), partial, acc);
+}
+
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
                      const void* fn, void* lout, double* partial, bool accumulate, double* ds,
-                     hipStream_t st) {
+                     bool nt, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
-    const int blocks = nitems, acc = accumulate ? 1 : 0;
+    const int acc = accumulate ? 1 : 0;
     switch (prec) {
-        case 0:
-            hipLaunchKernelGGL((adjoint_kernel<double, double>), dim3(blocks), dim3(256), 0, st,
-                               insts, items, nitems, static_cast<const double*>(lin),
-                               static_cast<const double*>(fn), static_cast<double*>(lout), partial,
-                               acc);
-            break;
-        case 1:
-            hipLaunchKernelGGL((adjoint_kernel<float, float>), dim3(blocks), dim3(256), 0, st,
-                               insts, items, nitems, static_cast<const float*>(lin),
-                               static_cast<const float*>(fn), static_cast<float*>(lout), partial,
-                               acc);
-            break;
-        default:
-            hipLaunchKernelGGL((adjoint_kernel<float, double>), dim3(blocks), dim3(256), 0, st,
-                               insts, items, nitems, static_cast<const float*>(lin),
-                               static_cast<const float*>(fn), static_cast<float*>(lout), partial,
-                               acc);
-            break;
+        case 0: launch_adjoint<double, double>(insts, items, nitems, lin, fn, lout, partial, acc, nt, st); break;
+        case 1: launch_adjoint<float, float>(insts, items, nitems, lin, fn, lout, partial, acc, nt, st); break;
+        default: launch_adjoint<float, double>(insts, items, nitems, lin, fn, lout, partial, acc, nt, st); break;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !ds) return e;
