@@ -308,7 +308,8 @@ struct mrt_ctx {
     Item* d_items_adj = nullptr;     // work items of the adjoint kernel
     int nitems_adj = 0;
     double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
-    double* d_partial = nullptr;     // 16 doubles per wave of an adjoint item: partial sums
+    double* d_partial = nullptr;     // rate-gradient partial sums: 16 doubles per adjoint item,
+                                     // then 64 rows for the reduction's first stage
     unsigned* d_health = nullptr;
     bool params_set = false, fields_set = false;
     std::string err;
@@ -391,7 +392,8 @@ int build_adjoint_items(mrt_ctx* c) {
     add_items(items, 0, c->nx, c->ny, adjoint_rows(c->nx, c->ny));
     HIPTRY(hipMalloc(&c->d_items_adj, items.size() * sizeof(Item)));
     HIPTRY(hipMemcpy(c->d_items_adj, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
-    HIPTRY(hipMalloc(&c->d_partial, items.size() * 4 * 16 * sizeof(double)));
+    // one partial row per item, then the reduction's 64 stage rows
+    HIPTRY(hipMalloc(&c->d_partial, (items.size() + 64) * 16 * sizeof(double)));
     c->nitems_adj = int(items.size());
     return MRT_OK;
 }

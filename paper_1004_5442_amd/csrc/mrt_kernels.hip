@@ -961,21 +961,18 @@ __global__ __launch_bounds__(256, 2) void step2_kernel(const Inst* __restrict__ 
 // columns by a load on one lane each.  Each of lam^{n+1}, f^n and lam^n then
 // crosses the memory interface once per cell (plus the band's two halo rows
 // of lam), 192 B per cell in FP32 storage.  Partial sums of the rate
-// gradient per wave go to `partial` (16 doubles per wave; with `accumulate`
-// they are added to what the row holds, so a sweep of many steps is reduced
-// once), reduced in a fixed order by reduce_partials.
+// gradient per item go to `partial` (16 doubles per item: the four waves'
+// sums added in a fixed order; with `accumulate` they are added to what the
+// row holds, so a sweep of many steps is reduced once), reduced in a fixed
+// order by reduce_stripes and reduce_partials.
 template <typename S, typename C, bool NT>
-__device__ __forceinline__ void adjoint_block(const Inst* __restrict__ P, int item, int x0, int y0,
+__device__ __forceinline__ void adjoint_block(ConstInst* __restrict__ P, int item, int x0, int y0,
                                               int y1, const S* __restrict__ lin,
                                               const S* __restrict__ fn, S* __restrict__ lout,
                                               double* __restrict__ partial, bool accumulate,
-                                              EdgeBuf<S>& lds) {
+                                              EdgeBuf<S>& lds, double (&red)[kWaves][12]) {
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const long long plane = P->plane;
-    const S* __restrict__ li = lin + P->off;
-    const S* __restrict__ fi = fn + P->off;
-    S* __restrict__ lo = lout + P->off;
     const int nx = P->nx;
     const int x = x0 + 64 * wv + lane;
     const bool act = x < nx;
@@ -984,12 +981,30 @@ __device__ __forceinline__ void adjoint_block(const Inst* __restrict__ P, int it
     const unsigned cx = unsigned(act ? x : P->col_hi);
     const unsigned xs = unsigned(act ? x : nx + 1);
     const C b = C(P->b), binv = C(P->binv), dt = C(P->dt);
-    auto ldl = [&](int i, unsigned row, unsigned col) -> S { return (li + (long long)i * plane)[row + col]; };
-    auto ldf = [&](int i, unsigned row, unsigned col) -> S { return (fi + (long long)i * plane)[row + col]; };
     const bool hmem = (wv == 0 && lane == 0) || (wv == kWaves - 1 && lane == 63);
     unsigned hx = cx;
     if (wv == 0 && lane == 0) hx = unsigned(x0 > 0 ? x0 - 1 : P->col_lo);
     if (wv == kWaves - 1 && lane == 63) hx = unsigned(x0 + 256 < nx ? x0 + 256 : P->col_hi);
+    // scalar row pointers at column -1 plus the lane's byte offset, as in
+    // step2_block (no vector address arithmetic per access)
+    const unsigned long long lib = reinterpret_cast<unsigned long long>(lin + P->off);
+    const unsigned long long fib = reinterpret_cast<unsigned long long>(fn + P->off);
+    const unsigned long long lob = reinterpret_cast<unsigned long long>(lout + P->off);
+    const unsigned long long pstep = (unsigned long long)P->plane * sizeof(S);
+    const unsigned bcx = (cx + 1u) * unsigned(sizeof(S)), bhx = (hx + 1u) * unsigned(sizeof(S));
+    const unsigned bxs = (xs + 1u) * unsigned(sizeof(S));
+    auto row_at = [&](unsigned long long base, unsigned o) {
+        return base + ((unsigned long long)o - 1u) * sizeof(S);
+    };
+    auto load_row = [&](unsigned long long base, unsigned o, unsigned boff, S (&r)[16], bool ymoving) {
+        unsigned long long a = row_at(base, o);
+        const unsigned bo = lane_off(boff);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            r[i] = (!ymoving || moves_y(i)) ? gload<S>(a, bo) : S(0);
+            if (i < 15) a = next_pop(a, pstep);
+        }
+    };
     const bool edge_lane = lane == 0 || lane == 63;
     const int eside = lane == 0 ? 0 : 1;
     const int nwave = lane == 0 ? wv - 1 : wv + 1;
@@ -1013,64 +1028,61 @@ __device__ __forceinline__ void adjoint_block(const Inst* __restrict__ P, int it
                     const S (&fc)[16], S (&fnx)[16], int y) {
         const bool more = y + 1 < y1;
         if (more) {
-            const unsigned on = row_offset(P, y + 2), of = row_offset(P, y + 1);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) rn[i] = ldl(i, on, cx);
-#pragma unroll
-            for (int i = 0; i < 16; ++i) fnx[i] = ldf(i, of, cx);
+            load_row(lib, row_offset(P, y + 2), bcx, rn, false);
+            load_row(fib, row_offset(P, y + 1), bcx, fnx, false);
         }
         const unsigned o = row_offset(P, y);
         S h[16];
         no_value(h);
         if (hmem) {
+            unsigned long long a = row_at(lib, o);
+            const unsigned bo = lane_off(bhx);
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (moves_x(i)) h[i] = ldl(i, o, hx);
+            for (int i = 0; i < 16; ++i) {
+                if (moves_x(i)) h[i] = gload<S>(a, bo);
+                if (i < 15) a = next_pop(a, pstep);
+            }
         } else if (hlds) {
             const int slot = y & 1;
 #pragma unroll
             for (int i = 0; i < 16; ++i)
                 if (moves_x(i)) h[i] = lds.v[slot][nwave][nside][xslot(i)];
         }
+        ConstInst* __restrict__ Pc = reload(P);
         C f[16], lam[16], coll[16], dsk[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             f[i] = C(fc[i]);
             lam[i] = C(r0[i]);
         }
-        cell_adjoint(f, lam, b, binv, P->sdt, dt, coll, dsk);
+        cell_adjoint(f, lam, b, binv, Pc->sdt, dt, coll, dsk);
         if (act) {
 #pragma unroll
             for (int k = 4; k < 16; ++k) acc[k] -= double(dsk[k]);
         }
+        unsigned long long a = row_at(lob, o);
+        const unsigned bo = lane_off(bxs);
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const S W = moves_x(i) ? from_left(r0[i], h[i]) : S(0);
             const S E = moves_x(i) ? from_right(r0[i], h[i]) : S(0);
-            S* dst = &(lo + (long long)i * plane)[o + xs];
             // mirrored neighbours: (E, W) and (N, So) in the (W, E), (So, N) slots
-            const S v = site_update(P, i, r0[i], E, W, rp[i], rm[i], S(coll[i]));
-            if constexpr (NT)
-                __builtin_nontemporal_store(v, dst);
-            else
-                *dst = v;
+            gstore<S, NT>(a, bo, site_update(Pc, i, r0[i], E, W, rp[i], rm[i], S(coll[i])));
+            if (i < 15) a = next_pop(a, pstep);
         }
         if (more) publish(rp, (y + 1) & 1);
         __syncthreads();
     };
 
     S A[16], B[16], Cw[16], D[16], F0[16], F1[16];
-    {
-        const unsigned om = row_offset(P, y0 - 1), o0 = row_offset(P, y0), op = row_offset(P, y0 + 1);
+    load_row(lib, row_offset(P, y0), bcx, B, false);
+    load_row(lib, row_offset(P, y0 + 1), bcx, Cw, false);
+    load_row(lib, row_offset(P, y0 - 1), bcx, A, true);
+    load_row(fib, row_offset(P, y0), bcx, F0, false);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            B[i] = ldl(i, o0, cx);
-            Cw[i] = ldl(i, op, cx);
-            A[i] = moves_y(i) ? ldl(i, om, cx) : S(0);
-            D[i] = S(0);
-            F0[i] = ldf(i, o0, cx);
-            F1[i] = S(0);
-        }
+    for (int i = 0; i < 16; ++i) {
+        D[i] = S(0);
+        F1[i] = S(0);
     }
     publish(B, y0 & 1);
     __syncthreads();
@@ -1083,7 +1095,8 @@ __device__ __forceinline__ void adjoint_block(const Inst* __restrict__ P, int it
         if (y >= y1) break;
         body(D, A, B, Cw, F1, F0, y); ++y;
     }
-    // wave reduction of the 12 non-trivial rate gradients
+    // wave reduction of the 12 non-trivial rate gradients, then the four
+    // waves' sums in a fixed order into the item's partial row
 #pragma unroll
     for (int k = 4; k < 16; ++k) {
         double v = acc[k];
@@ -1092,12 +1105,15 @@ __device__ __forceinline__ void adjoint_block(const Inst* __restrict__ P, int it
         acc[k] = v;
     }
     if (lane == 0) {
-        double* row = &partial[((long long)item * kWaves + wv) * 16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const double v = k < 4 ? 0.0 : acc[k];
-            row[k] = accumulate ? row[k] + v : v;
-        }
+        for (int k = 4; k < 16; ++k) red[wv][k - 4] = acc[k];
+    }
+    __syncthreads();
+    if (wv == 0 && lane < 16) {
+        double* row = &partial[(long long)item * 16];
+        const double v = lane < 4 ? 0.0
+                                  : ((red[0][lane - 4] + red[1][lane - 4]) + red[2][lane - 4]) + red[3][lane - 4];
+        row[lane] = accumulate ? row[lane] + v : v;
     }
 }
 
@@ -1115,16 +1131,52 @@ __global__ __launch_bounds__(256, (adjoint_waves<S>())) void adjoint_kernel(cons
                                                          double* __restrict__ partial,
                                                          int accumulate) {
     __shared__ EdgeBuf<S> lds;
+    __shared__ double red[kWaves][12];
+    ConstInst* cinsts = (ConstInst*)insts;
+    ConstItem* citems = (ConstItem*)items;
     // XCD-aware item order as in step_kernel
     const int per = (nitems + 7) >> 3;
     for (int q = blockIdx.x; q < 8 * per; q += gridDim.x) {
         const int w = (q & 7) * per + (q >> 3);
         if (w >= nitems) continue;
-        const Item it = items[w];
-        adjoint_block<S, C, NT>(insts + it.inst, w, it.x0, it.y0, it.y1, lin, fn, lout, partial,
-                                accumulate != 0, lds);
+        const int inst = citems[w].inst, x0 = citems[w].x0, y0 = citems[w].y0, y1 = citems[w].y1;
+        adjoint_block<S, C, NT>(cinsts + inst, w, x0, y0, y1, lin, fn, lout, partial,
+                                accumulate != 0, lds, red);
         __syncthreads();   // the next item reuses the edge buffer
     }
+}
+
+// First stage of the rate-gradient reduction: block g of the launch sums
+// the partial rows [g * per, min(n, (g + 1) * per)) into stage[g][16]
+// (thread t: column t % 16, rows t / 16, t / 16 + 16, ... of the range,
+// four running sums added in a fixed order, then the 16 stripes pairwise);
+// reduce_partials then adds the stage rows into ds.  Many blocks read the
+// partial rows in parallel (one 1024-thread block reading 2,048 rows took
+// 23 us of a 2048^2 adjoint step); the order of every addition is fixed, so
+// ds is bitwise reproducible.
+constexpr int kStageBlocks = 64;
+constexpr int kSingleStageRows = 1024;
+__global__ __launch_bounds__(256) void reduce_stripes(const double* __restrict__ partial, int n,
+                                                      int per, double* __restrict__ stage) {
+    __shared__ double red[16][16];
+    const int t = threadIdx.x, k = t & 15, stripe = t >> 4;
+    const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+    double a[4] = {0, 0, 0, 0};
+    int i = r0 + stripe;
+    for (; i + 48 < r1; i += 64) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] += partial[(long long)(i + 16 * j) * 16 + k];
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)      // fewer than four rows left
+        if (i + 16 * j < r1) a[j] += partial[(long long)(i + 16 * j) * 16 + k];
+    red[stripe][k] = (a[0] + a[1]) + (a[2] + a[3]);
+    __syncthreads();
+    for (int half = 8; half >= 1; half >>= 1) {
+        if (stripe < half) red[stripe][k] += red[stripe + half][k];
+        __syncthreads();
+    }
+    if (t < 16) stage[blockIdx.x * 16 + t] = red[0][t];
 }
 
 // ds[k] += sum over the n partial rows of partial[row][k]: one block of
@@ -1518,9 +1570,10 @@ hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool r
     }
 }
 
-// One adjoint step; partial rows (kWaves per item) are overwritten
+// One adjoint step; partial rows (one per item) are overwritten
 // (accumulate = false) or added to (true); ds != NULL: then reduce the
-// partial rows into ds.  nt: non-temporal stores of lam^n.
+// partial rows into ds (partial must hold nitems + kStageBlocks rows of 16
+// doubles).  nt: non-temporal stores of lam^n.
 template <typename S, typename C>
 void launch_adjoint(const Inst* insts, const Item* items, int nitems, const void* lin,
                     const void* fn, void* lout, double* partial, int acc, bool nt, hipStream_t st) {
@@ -1547,7 +1600,20 @@ hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !ds) return e;
-    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kReduceThreads), 0, st, partial, nitems * kWaves, ds);
+    // a few rows: one block sums them (one launch; small grids are
+    // latency-bound); else two stages.  partial holds nitems rows, then
+    // kStageBlocks rows of stage sums
+    if (nitems <= kSingleStageRows) {
+        hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kReduceThreads), 0, st, partial, nitems, ds);
+        return hipGetLastError();
+    }
+    double* stage = partial + (long long)nitems * 16;
+    const int per = (nitems + kStageBlocks - 1) / kStageBlocks;
+    const int blocks = (nitems + per - 1) / per;
+    hipLaunchKernelGGL(reduce_stripes, dim3(blocks), dim3(256), 0, st, partial, nitems, per, stage);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_partials, dim3(1), dim3(kReduceThreads), 0, st, stage, blocks, ds);
     return hipGetLastError();
 }
 
