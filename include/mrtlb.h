@@ -236,6 +236,20 @@ const char* mrt_last_error(const mrt_ctx* ctx);
 int mrt_adjoint_step(mrt_ctx* ctx, const void* lam_next, const void* f_n, void* lam_n,
                      double* ds);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * adjoint step as mrt_adjoint_step (same kernels, same arguments, bitwise the
+ * same lam_n and ds), with the rate-gradient partial sums in a fixed 1 MiB
+ * device array of the library instead of the context's own buffer.  The call
+ * allocates and frees nothing.  Grids of up to 8128 adjoint work items
+ * (256-column chunks of row bands; e.g. 4096 x 4096 uses 4096): larger ones
+ * get MRT_EINVAL with a message.  Every call on one GPU shares that array:
+ * calls that overlap on one GPU (from several contexts or streams at once)
+ * race; calls ordered on one stream do not (each overwrites the rows it
+ * reads).  Errors as mrt_adjoint_step. */
+int mrt_adjoint_step_noalloc(mrt_ctx* ctx, const void* lam_next, const void* f_n, void* lam_n,
+                             double* ds);
+
 /* Forward pass that keeps sqrt(N)-style checkpoints for a later
  * mrt_adjoint_sweep: for n = 0 .. nsteps-1, copies f^n into
  * checkpoints[n / segment] when n % segment == 0, then steps (as

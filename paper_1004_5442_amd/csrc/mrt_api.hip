@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -49,6 +50,45 @@ hipError_t k_import(int prec, const Inst* P, long long cells, const double* in, 
 
 using mrt::Inst;
 using mrt::Item;
+
+// Scratch of mrt_adjoint_step_noalloc: the rate-gradient partial rows of one
+// adjoint step (one row of 16 doubles per work item, then the reduction's 64
+// stage rows), in a fixed device array instead of a library allocation, so
+// that the call allocates nothing.  1 MiB: grids of up to 8128 adjoint work
+// items.  Each device holds its own copy until the process ends; host code
+// uses only the per-device address resolved by scratch_address(), never the
+// array's name.
+constexpr int kScratchDoubles = 1 << 17;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, resolved once per
+// device (hipGetSymbolAddress with that device current); nullptr on error.
+double* scratch_address(std::string& err) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        err = "no current HIP device (or device index >= 64) for the static scratch";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
 
 namespace {
 
@@ -310,6 +350,8 @@ struct mrt_ctx {
     double* d_stage = nullptr;       // 4 * nx * ny doubles: field staging
     double* d_partial = nullptr;     // rate-gradient partial sums: 16 doubles per adjoint item,
                                      // then 64 rows for the reduction's first stage
+    double* d_scratch = nullptr;     // the static scratch on this context's device
+    std::string scratch_err;         // why d_scratch could not be resolved
     unsigned* d_health = nullptr;
     bool params_set = false, fields_set = false;
     std::string err;
@@ -480,6 +522,9 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     for (int k = 0; k < 4; ++k) c->inst.bc[k] = bc[k];
     if (build_items(c, default_rows(nx, ny)) != MRT_OK) return fail(MRT_EDEVICE);
     if (build_adjoint_items(c) != MRT_OK) return fail(MRT_EDEVICE);
+    // address of the static scratch on this device (mrt_adjoint_step_noalloc;
+    // a failure here is reported by that call, the others do not need it)
+    c->d_scratch = scratch_address(c->scratch_err);
     c->nt = (long long)bytes > kNonTemporalBytes;
     c->walls = has_kind(bc, MRT_BC_REFLECT) && (long long)nx * ny <= kWallsInKernelCells;
     // FP32 storage grids larger than the last-level cache (HBM-bound with
@@ -913,6 +958,31 @@ int mrt_adjoint_step(mrt_ctx* c, const void* lam_next, const void* f_n, void* la
         return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
     HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, lam_next, f_n, lam_n,
                           c->d_partial, false, ds, c->nt, c->stream));
+    return MRT_OK;
+}
+
+int mrt_adjoint_step_noalloc(mrt_ctx* c, const void* lam_next, const void* f_n, void* lam_n,
+                             double* ds) {
+    if (!c) return MRT_EINVAL;
+    std::string& ctx_err = c->err;
+    if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
+    if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
+    if (c->scheme) return ctx_fail(c, MRT_EINVAL, "the adjoint is of the default scheme only");
+    if (!lam_next || !f_n || !lam_n || !ds || lam_n == lam_next)
+        return ctx_fail(c, MRT_EINVAL, "bad adjoint buffers");
+    if (!c->d_scratch) return ctx_fail(c, MRT_EDEVICE, c->scratch_err);
+    const long long need = ((long long)c->nitems_adj + 64) * 16;
+    if (need > kScratchDoubles) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf,
+                      "grid too large for the static scratch: %d adjoint work items, at most %d",
+                      c->nitems_adj, kScratchDoubles / 16 - 64);
+        return ctx_fail(c, MRT_EINVAL, buf);
+    }
+    // the kernel overwrites every partial row it reduces (no accumulation),
+    // so nothing has to be cleared first
+    HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, lam_next, f_n, lam_n,
+                          c->d_scratch, false, ds, c->nt, c->stream));
     return MRT_OK;
 }
 

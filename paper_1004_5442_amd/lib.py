@@ -71,6 +71,7 @@ _proto = {
     "mrt_destroy": (None, [c_void_p]),
     "mrt_last_error": (ctypes.c_char_p, [c_void_p]),
     "mrt_adjoint_step": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mrt_adjoint_step_noalloc": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mrt_step_buffers": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mrt_step_checkpointed": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, POINTER(c_void_p)]),
     "mrt_adjoint_sweep": (c_int, [c_void_p, POINTER(c_void_p), c_int, c_int, POINTER(c_void_p),
