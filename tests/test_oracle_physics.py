@@ -269,13 +269,16 @@ def test_linear_stability_interval():
     assert stability.max_amplification(st, outside, 17) > 1.5
 
 
-def test_small_perturbations_follow_the_amplification_matrix():
+@pytest.mark.parametrize("reading", ["unsplit", "split"])
+def test_small_perturbations_follow_the_amplification_matrix(reading):
     """The linear-stability tool is the scheme's own linearisation: a small
     Fourier perturbation of a uniform moving equilibrium, advanced by the
-    nonlinear oracle step, equals G(theta)^N applied to it (G from
-    oracle/stability.py), to first order in the amplitude."""
+    nonlinear oracle step (unsplit, or the collide-then-convect option),
+    equals G(theta)^N applied to it (G from oracle/stability.py), to first
+    order in the amplitude."""
     n, N, eps = 16, 25, 1e-6
-    p = mrt.Params(gamma=1.4, s=rates(3e3, 6e3, 0.71, 8e3), dt=1e-4, dx=1.0 / n, dy=1.0 / n)
+    p = mrt.Params(gamma=1.4, s=rates(3e3, 6e3, 0.71, 8e3), dt=1e-4, dx=1.0 / n, dy=1.0 / n,
+                   split=(reading == "split"))
     base = (1.0, 0.3, -0.2, 0.9)
     f0 = mrt.feq(*base, p.b).reshape(16, 1, 1)
     rng = np.random.default_rng(2)
@@ -289,8 +292,40 @@ def test_small_perturbations_follow_the_amplification_matrix():
         f = mrt.step(f, p)
     # Fourier component at (kx, ky): the cosine's e^{+i phase} half
     got = 2.0 * np.mean((f - f0) * np.exp(-1j * phase), axis=(1, 2)) / eps
-    G = stability.amplification_matrix(base, p, tx, ty)
+    G = stability.amplification_matrix(base, p, tx, ty, reading)
     want = np.linalg.matrix_power(G, N) @ v
     assert np.allclose(got, want, rtol=0, atol=1e-5 * np.abs(want).max())
     # and the transfer is not trivial: the mode changed over the run
     assert np.abs(want - v).max() > 1e-2 * np.abs(v).max()
+
+
+def test_reading_amplifications_reduce_to_their_textbook_factors():
+    """Every reading of the time/space passage in the stability tool: with
+    theta = 0 (no convection) each mode of the linear collision K = dt J_C,
+    eigenvalue k, is multiplied by the scalar factor of its time integrator
+    (forward Euler 1 - k, split the same, Taylor 1 - k + k^2/2, Crank-Nicolson
+    (1 - k/2)/(1 + k/2), exact e^-k); with every rate zero (no collision) each
+    reading is the Lax-Wendroff symbol 1 - i c sin(theta) + c^2 (cos(theta) - 1)
+    per population."""
+    st = (1.1, 0.4, -0.3, 0.8)
+    p = mrt.Params(gamma=1.4, s=rates(3e3, 6e3, 0.71, 8e3), dt=1e-4, dx=1e-3, dy=1e-3)
+    from oracle.adjoint import collision_jacobian
+    f0 = mrt.feq(*st, p.b).reshape(16, 1, 1)
+    k = np.linalg.eigvals(p.dt * collision_jacobian(f0, p)[:, :, 0, 0])
+    factors = {"unsplit": 1 - k, "split": 1 - k, "rhs_taylor": 1 - k + k * k / 2,
+               "trapezoid": (1 - k / 2) / (1 + k / 2), "exp_collision": np.exp(-k)}
+    for reading in stability.READINGS:
+        ev = np.linalg.eigvals(stability.amplification_matrix(st, p, 0.0, 0.0, reading))
+        want = factors[reading]
+        # match the two spectra as multisets
+        d = np.abs(ev[:, None] - want[None, :])
+        assert np.max(np.min(d, axis=1)) < 1e-9 and np.max(np.min(d, axis=0)) < 1e-9, reading
+    p0 = mrt.Params(gamma=1.4, s=np.zeros(16), dt=1e-4, dx=1e-3, dy=2e-3)
+    vx, vy, _ = mrt.velocity_set()
+    cx, cy = vx * p0.dt / p0.dx, vy * p0.dt / p0.dy
+    tx, ty = 0.7, -1.9
+    sym = (1 - 1j * cx * np.sin(tx) + cx ** 2 * (np.cos(tx) - 1)
+           - 1j * cy * np.sin(ty) + cy ** 2 * (np.cos(ty) - 1))
+    for reading in stability.READINGS:
+        G = stability.amplification_matrix(st, p0, tx, ty, reading)
+        assert np.allclose(G, np.diag(sym), rtol=0, atol=1e-13), reading

@@ -3,15 +3,16 @@ under the library's reading of the discretisation (unsplit forward Euler,
 per-axis Lax-Wendroff), from the oracle's amplification spectrum.  It
 explains which runs of that section survive the paper's 130,000 steps."""
 import numpy as np
+import pytest
 
 from oracle import mrt, stability
 from paper_1004_5442_amd import workloads as W
 
 
-def _amp(gamma, srt, state):
+def _amp(gamma, srt, state, reading="unsplit", n_theta=65):
     c = W.strong_shock_tube(gamma, srt, ny=1)
     p = mrt.Params(gamma=gamma, s=c.s, dt=c.dt, dx=c.dx, dy=c.dy)
-    return stability.max_amplification(state, p, n_theta=65, one_d=True)
+    return stability.max_amplification(state, p, n_theta=n_theta, one_d=True, reading=reading)
 
 
 def test_gamma_7_5_runs_are_stable_in_1d():
@@ -36,3 +37,44 @@ def test_2d_modes_destabilise_the_mrt_tube():
     worst = max(float(np.max(np.abs(stability.mode_rates(W.STRONG_SHOCK_LEFT, p, tx, np.pi / 2))))
                 for tx in np.linspace(-np.pi, np.pi, 65))
     assert worst > 1.0 + 1e-4
+
+
+# growth per step of the gamma = 5/3 MRT run at the hot left state under each
+# reading (97 phase angles), as printed in the design notes
+READING_GROWTH_5_3 = {"unsplit": 2.05e-4, "split": 1.46e-4, "rhs_taylor": 1.82e-4,
+                      "trapezoid": 1.80e-4, "exp_collision": 1.81e-4}
+
+
+def test_no_reading_of_the_discretisation_passage_stabilises_gamma_5_3():
+    """Section (b) reports the gamma = 5/3 MRT run of the strong-shock
+    problem as successful.  Every reading of the time/space passage the
+    stability tool forms (forward Euler unsplit or split either way round,
+    Lax-Wendroff's Taylor term on the whole right-hand side collision
+    included, a Crank-Nicolson or an exact collision) keeps gamma = 7/5 stable
+    at both states and leaves the hot left state of gamma = 5/3 growing by
+    1.5-2.1e-4 per step (e^19 to e^27 over the 130,000 steps)."""
+    for reading in stability.READINGS:
+        for st in (W.STRONG_SHOCK_LEFT, W.STRONG_SHOCK_RIGHT):
+            assert _amp(1.4, False, st, reading, 97) <= 1.0 + 1e-7, reading
+        g = _amp(5.0 / 3.0, False, W.STRONG_SHOCK_LEFT, reading, 97)
+        assert g - 1.0 == pytest.approx(READING_GROWTH_5_3[reading], rel=0.02), (reading, g)
+
+
+def test_hot_state_is_unstable_before_discretisation():
+    """Why no reading helps: the model itself, continuous in time and space
+    (eigenvalues of -i k v_x - J_C), has modes growing at grid-scale
+    wavenumbers at the hot left state, ~1e4 per unit time at k dx = pi for
+    either gamma (equilibria with negative populations make the linearised
+    collision not dissipative there).  Only the Lax-Wendroff damping,
+    c^2 (1 - cos theta) per step at Courant numbers of at most 3e-3, holds
+    them down, and at gamma = 5/3 it falls short; at the cold right state the
+    continuous model is stable for gamma = 7/5."""
+    for gamma in (1.4, 5.0 / 3.0):
+        c = W.strong_shock_tube(gamma, False, ny=1)
+        p = mrt.Params(gamma=gamma, s=c.s, dt=c.dt, dx=c.dx, dy=c.dy)
+        assert stability.semi_discrete_growth(W.STRONG_SHOCK_LEFT, p, np.pi) > 5e3
+    c = W.strong_shock_tube(1.4, False, ny=1)
+    p = mrt.Params(gamma=1.4, s=c.s, dt=c.dt, dx=c.dx, dy=c.dy)
+    worst = max(stability.semi_discrete_growth(W.STRONG_SHOCK_RIGHT, p, th)
+                for th in np.linspace(0.01, np.pi, 64))
+    assert worst < 1e-6
