@@ -86,12 +86,14 @@ constexpr bool moves_y(int i) { return i < 8 ? (i & 1) == 1 : true; }
 // error Neumaier's ordered form recovers, without its compare and select)
 // and accumulated in c.
 __device__ __forceinline__ void neumaier(float& s, float& c, float x) {
+    MRT_CONTRACT_IN_EXPRESSIONS
     const float t = s + x;
     const float bp = t - s, ap = t - bp;
     c += (s - ap) + (x - bp);
     s = t;
 }
 __device__ __forceinline__ void conserved_compensated(const float f[16], float q[4]) {
+    MRT_CONTRACT_IN_EXPRESSIONS
     const float sp[4] = {1.0f, 6.0f, float(kR2), float(kR32)};
     const float eps[4] = {7.25f, 36.0f, 4.0f, 9.0f};
     float s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};

@@ -325,6 +325,30 @@ def srt_rates(tau: float) -> np.ndarray:
     return s
 
 
+def paper_riemann2d(n: int = 500, srt: bool = False, srt_rate: float = 3e3,
+                    width_cells: float = 0.0, nsteps: int = 12000) -> Case:
+    """The paper's own two-dimensional Riemann problem (section (c)): the four
+    printed quadrant states (PAPER_QUADRANTS; quadrant 1 upper right, counted
+    anticlockwise, the corner at the centre), gamma = 1.4 (the printed Mach
+    numbers 1.358 and 3.1444 hold for it), dx = dy = 0.002, dt = 1e-5,
+    t = 0.12 after 12,000 steps.  MRT: s_8 = s_9 = 2e4, every other rate 3e3
+    (so Pr = s_8/s_6 = 6.7).  The paper runs SRT without giving its rate:
+    srt_rate sets every rate (default 3e3, the MRT viscous rate).  The paper
+    gives no domain: [0, 1]^2 (n = 500) with outflow on every side.  Sharp
+    initial interfaces by default (width_cells = 0)."""
+    c = riemann2d(n=n, states=PAPER_QUADRANTS, width_cells=width_cells, nsteps=nsteps)
+    if srt:
+        s = srt_rates(1.0 / srt_rate)
+    else:
+        s = np.zeros(16)
+        s[4:] = 3e3
+        s[7] = s[8] = 2e4
+    kind = f"srt{srt_rate:g}" if srt else "mrt"
+    return Case(f"paper_riemann2d_{kind}_{n}x{n}", n, n, c.rho, c.ux, c.uy, c.T, gamma=1.4,
+                Pr=float(s[7] / s[5]), s=s, dt=1e-5, dx=1.0 / n, dy=1.0 / n, bc=c.bc,
+                side_state=c.side_state, nsteps=nsteps)
+
+
 def strong_shock_tube(gamma: float = 1.4, srt: bool = False, nx: int = 1100, ny: int = 1,
                       x0: float = 0.25, nsteps: int = 130000, width_cells: float = 0.0) -> Case:
     """The paper's one-dimensional Riemann problem run with the 2D model:

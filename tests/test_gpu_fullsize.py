@@ -302,34 +302,65 @@ def test_shock_bubble_fp32_against_fp64_50_steps():
     assert all(err[k] < tol[k] for k in err), (err, tol)
 
 
+_RIEMANN2D = {}
+
+
+def _riemann2d_2000():
+    """The 2D Riemann workload as configured (1024^2, 2000 steps) in FP64,
+    FP32 storage with FP64 collision and pure FP32 (autotuned launches); the
+    FP32 forms' per-field errors against the FP64 kernel over the whole
+    field, and the FP32-storage tolerances of a 1024 x 8 band of it."""
+    if not _RIEMANN2D:
+        n, steps = 1024, 2000
+        band = W.riemann2d(n=n, ny=8, seed=0)
+        want, _ = oracle_run(band, steps)
+        _RIEMANN2D["tol"] = fp32_tolerances(band, steps, want)
+        case = W.riemann2d(n=n, seed=0)
+        fields = {}
+        for precision in ("fp64", "fp32_eq64", "fp32"):
+            print(f"case {case.name} {precision} {steps} steps", flush=True)
+            s = solver_for_case(case, precision)
+            s.autotune(4)
+            s.step(steps)
+            fields[precision] = [f.double() for f in s.moments_device()]
+            s.sync()
+            s.close()
+        r64, u64, v64, T64 = fields["fp64"]
+        sp = max(float(torch.sqrt(u64 * u64 + v64 * v64).max()), float(torch.sqrt(T64.max())))
+        for precision in ("fp32_eq64", "fp32"):
+            r, u, v, T = fields[precision]
+            _RIEMANN2D[precision] = {
+                "rho": float((r - r64).abs().max() / r64.abs().max()),
+                "u": max(float((u - u64).abs().max()), float((v - v64).abs().max())) / sp,
+                "T": float((T - T64).abs().max() / T64.abs().max())}
+            print(precision, "vs fp64", _RIEMANN2D[precision], flush=True)
+    return _RIEMANN2D
+
+
 def test_riemann2d_1024_fp32_forms_against_fp64_2000_steps():
-    """The 2D Riemann workload as configured (1024^2, 2000 steps): both FP32
-    forms against the FP64 kernel over the whole field, per field.  FP32
-    storage with FP64 collision: within twice the FP32-storage error the
-    oracle shows on a 1024 x 8 band of it after 2000 steps (at least 1e-5).
-    Pure FP32, whose collision arithmetic also rounds to FP32 (measured 1.3
-    to 2.7 times the other form's error here): within four times it."""
-    n, steps = 1024, 2000
-    band = W.riemann2d(n=n, ny=8, seed=0)
-    want, _ = oracle_run(band, steps)
-    tol = fp32_tolerances(band, steps, want)
-    case = W.riemann2d(n=n, seed=0)
-    fields = {}
-    for precision in ("fp64", "fp32_eq64", "fp32"):
-        print(f"case {case.name} {precision} {steps} steps", flush=True)
-        s = solver_for_case(case, precision)
-        s.autotune(4)
-        s.step(steps)
-        fields[precision] = [f.double() for f in s.moments_device()]
-        s.sync()
-        s.close()
-    r64, u64, v64, T64 = fields["fp64"]
-    sp = max(float(torch.sqrt(u64 * u64 + v64 * v64).max()), float(torch.sqrt(T64.max())))
+    """Regression bound of both FP32 forms on the 2D Riemann workload as
+    configured: FP32 storage with FP64 collision within twice the
+    FP32-storage error the oracle shows on a 1024 x 8 band of it after 2000
+    steps (at least 1e-5); pure FP32, whose collision arithmetic also rounds
+    to FP32 (measured 1.3 to 2.7 times the other form's error here), within
+    four times it."""
+    res = _riemann2d_2000()
     for precision, factor in (("fp32_eq64", 1.0), ("fp32", 2.0)):
-        r, u, v, T = fields[precision]
-        err = {"rho": float((r - r64).abs().max() / r64.abs().max()),
-               "u": max(float((u - u64).abs().max()), float((v - v64).abs().max())) / sp,
-               "T": float((T - T64).abs().max() / T64.abs().max())}
-        bound = {k: factor * v for k, v in tol.items()}
+        err = res[precision]
+        bound = {k: factor * v for k, v in res["tol"].items()}
         print(precision, "vs fp64", err, "tolerance", bound, flush=True)
         assert all(err[k] < bound[k] for k in err), (precision, err, bound)
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp32"])
+def test_riemann2d_1024_stated_tolerance(precision):
+    """The stated target itself, per field and form: 1e-5 relative on rho, u
+    and T after the configured 2000 steps of the 2D Riemann workload, against
+    the FP64 kernel (whose own distance to the oracle is at the 1e-12 level
+    on the sampled patches).  Measured: FP32 storage with FP64 collision
+    rho 5.9e-6, u 6.2e-6, T 7.5e-6; pure FP32 rho 7.3e-6, u 6.4e-6, T 8.5e-6
+    (it missed the target at 1.1e-5 / 1.7e-5 while its FP32 transforms let
+    the compiler fuse products across statements, differently per row)."""
+    err = _riemann2d_2000()[precision]
+    print(precision, "stated-tolerance check", err, flush=True)
+    assert all(v < 1e-5 for v in err.values()), (precision, err)

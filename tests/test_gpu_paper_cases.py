@@ -1,6 +1,7 @@
 """The paper's own test problems on the GPU: the Richtmyer-Meshkov
-instability (section (d)) and the strong-shock Riemann problem of section
-(b) in its MRT and SRT forms.
+instability (section (d)), the strong-shock Riemann problem of section (b)
+and the two-dimensional Riemann problem of section (c), in their MRT and SRT
+forms.
 
 Parity: full-size runs against the FP64 oracle on the same inputs.  Physics:
 the paper's claim that MRT shows weaker oscillations at the discontinuities
@@ -134,3 +135,56 @@ def test_strong_shock_gamma_5_3_mrt_instability_is_detected():
         s.step(case.nsteps - 20000)
         s.sync()
     s.close()
+
+
+def test_paper_riemann2d_matches_oracle_first_steps():
+    """Section (c)'s two-dimensional Riemann problem at its printed size
+    (500 x 500, dx = 0.002, dt = 1e-5, sharp interfaces), MRT rates, FP64:
+    the whole grid after 20 steps against the oracle at 1e-12 of the
+    population scale."""
+    case = W.paper_riemann2d()
+    want, p = oracle_run(case, 20)
+    s = solver_for_case(case, "fp64")
+    s.step(20)
+    got = s.populations()
+    s.close()
+    err = float(np.max(np.abs(got - want)) / np.abs(want).max())
+    print("paper 2D Riemann, 20 steps: max population error", err, flush=True)
+    assert err <= 1e-12
+
+
+def test_paper_riemann2d_mrt_survives_where_srt_fails():
+    """The paper's claim for its 2D Riemann problem (section (c)): with its
+    parameters the MRT run recovers the flow to t = 0.12 where the SRT
+    version fails.  FP64, sharp interfaces as printed: the MRT run stays
+    healthy for all 12,000 steps and its density is symmetric about the
+    diagonal x = y like the initial data (to 1e-8 of its scale); the SRT run
+    at the MRT viscous rate (every rate 3e3; the paper does not print its SRT
+    rate) turns non-physical before t = 0.12 (measured near step 9,500), and
+    so do SRT runs at rates 2e4 and 1e5 (earlier)."""
+    case = W.paper_riemann2d()
+    s = solver_for_case(case, "fp64")
+    for k in range(case.nsteps // 2000):
+        s.step(2000)
+        s.sync()
+        print(f"MRT healthy at step {2000 * (k + 1)}", flush=True)
+    rho, ux, uy, T = s.moments()
+    s.close()
+    asym = float(np.max(np.abs(rho - rho.T)) / rho.max())
+    print("MRT density range", rho.min(), rho.max(), "diagonal asymmetry", asym, flush=True)
+    assert asym < 1e-8
+    assert rho.min() > 0.05 and rho.max() < 3.0
+    for rate in (3e3, 2e4, 1e5):
+        srt = W.paper_riemann2d(srt=True, srt_rate=rate)
+        s = solver_for_case(srt, "fp64")
+        failed_at = None
+        for k in range(srt.nsteps // 500):
+            s.step(500)
+            try:
+                s.sync()
+            except UnstableError:
+                failed_at = 500 * (k + 1)
+                break
+        s.close()
+        print(f"SRT rate {rate:g}: unhealthy by step {failed_at}", flush=True)
+        assert failed_at is not None and failed_at <= srt.nsteps

@@ -78,3 +78,22 @@ def test_hot_state_is_unstable_before_discretisation():
     worst = max(stability.semi_discrete_growth(W.STRONG_SHOCK_RIGHT, p, th)
                 for th in np.linspace(0.01, np.pi, 64))
     assert worst < 1e-6
+
+
+def test_paper_riemann2d_quadrant_growth_rates():
+    """Linear stability of the four printed quadrant states of section (c)
+    at the paper's parameters (dx = 0.002, dt = 1e-5; MRT s_8 = s_9 = 2e4,
+    other rates 3e3): quadrant 1 is stable, quadrants 2 and 4 grow by
+    ~4.9e-4 per step and the cold supersonic quadrant 3 (T = 0.21, Mach 3.14)
+    by ~1.55e-3: e^18.6 over the 12,000 steps.  Rounding seeds that mode: FP64
+    rounding (1e-16) stays far below O(1) (~1e-8) while FP32 storage rounding
+    (6e-8) reaches it, which is why the FP64 run reaches t = 0.12 and the
+    FP32-storage run breaks down near step 11,500."""
+    c = W.paper_riemann2d(n=50)
+    p = mrt.Params(gamma=1.4, s=c.s, dt=1e-5, dx=0.002, dy=0.002)
+    g = [stability.max_amplification(st, p, n_theta=33) - 1.0 for st in W.PAPER_QUADRANTS]
+    assert g[0] < 1e-12
+    assert g[1] == pytest.approx(4.87e-4, rel=0.05) and g[3] == pytest.approx(g[1], rel=1e-6)
+    assert g[2] == pytest.approx(1.55e-3, rel=0.05)
+    growth = np.exp(g[2] * 12000)
+    assert 1e-16 * growth < 1e-6 < 6e-8 * growth

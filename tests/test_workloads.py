@@ -144,3 +144,19 @@ def test_one_row_oracle_equals_full_tube_oracle():
     row, _ = oracle_run(one_row(c), 60)
     for j in range(c.ny):
         assert np.array_equal(full[:, j], row[:, 0])
+
+
+def test_paper_riemann2d_layout():
+    """Section (c): quadrant i holds the printed state i (1 upper right,
+    counted anticlockwise), sharp interfaces through the centre, the printed
+    rates and time step on the printed 0.002 grid."""
+    c = W.paper_riemann2d()
+    assert (c.nx, c.ny, c.dx, c.dy, c.dt, c.nsteps) == (500, 500, 0.002, 0.002, 1e-5, 12000)
+    corners = {(-1, -1): 0, (-1, 0): 1, (0, 0): 2, (0, -1): 3}   # (row, col) -> quadrant index
+    for (j, i), q in corners.items():
+        got = (c.rho[j, i], c.ux[j, i], c.uy[j, i], c.T[j, i])
+        assert np.allclose(got, W.PAPER_QUADRANTS[q]), (q, got)
+    assert set(np.unique(c.rho)) == {s[0] for s in W.PAPER_QUADRANTS}
+    assert c.s[7] == c.s[8] == 2e4 and np.all(np.delete(c.s[4:], [3, 4]) == 3e3)
+    srt = W.paper_riemann2d(srt=True, srt_rate=2e4)
+    assert np.all(srt.s[4:] == 2e4) and np.all(srt.s[:4] == 0)
