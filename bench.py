@@ -147,8 +147,7 @@ def _configured_solver(case, precision, autotune, tile_rows, scheme, per_pass):
     if per_pass == 2:
         s.set_steps_per_pass(2, tile_rows)
     elif tile_rows:
-        if precision != "fp64":
-            s.set_steps_per_pass(1, 0)
+        s.set_steps_per_pass(1, 0)
         s.set_tile(tile_rows)
     elif autotune:
         s.autotune(4)
@@ -165,7 +164,7 @@ def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, sche
     if autotune and not tile_rows and not per_pass:
         heat.set_tile(*s.tile())
         k, r = s.steps_per_pass()
-        if precision != "fp64" and not scheme:
+        if not scheme:
             heat.set_steps_per_pass(k, r if k == 2 else 0)
     pre = _preheat(heat.step, max_steps=case.nsteps)
     heat.close()
@@ -435,9 +434,17 @@ def extra_legs(head, prec, steps):
                 "roofline_frac": roofline(head, prec, r1)["frac"]}
 
     def fp64():
+        # the library's default at this size: two steps per pass, 32-row bands
+        r64 = time_solver(head, "fp64", k, 3, tile_rows=HEADLINE_BAND_ROWS, per_pass=2)
+        r64["steps"] = k
+        return {"mlups": round(r64["mlups"], 1), "steps_per_pass": 2, "band_rows": HEADLINE_BAND_ROWS,
+                "roofline_frac": roofline(head, "fp64", r64)["frac"]}
+
+    def fp64_one_step():
         r64 = time_solver(head, "fp64", k, 3, tile_rows=HEADLINE_TILE_ROWS)
         r64["steps"] = k
-        return {"mlups": round(r64["mlups"], 1), "roofline_frac": roofline(head, "fp64", r64)["frac"]}
+        return {"mlups": round(r64["mlups"], 1), "band_rows": HEADLINE_TILE_ROWS,
+                "roofline_frac": roofline(head, "fp64", r64)["frac"]}
 
     def fp32():
         r32 = time_solver(head, "fp32", k, 3, tile_rows=HEADLINE_BAND_ROWS, per_pass=2)
@@ -476,6 +483,7 @@ def extra_legs(head, prec, steps):
     return {
         "fp32_eq64_one_step_per_pass": one_step,
         "fp64_same_grid": fp64,
+        "fp64_one_step_per_pass": fp64_one_step,
         "fp32_same_grid": fp32,
         "riemann2d_1024_fp32_eq64": riemann("fp32_eq64"),
         "riemann2d_1024_fp64": riemann("fp64"),

@@ -128,7 +128,7 @@ int mrt_set_fields(mrt_ctx* ctx, const double* rho, const double* ux, const doub
 
 /* Advance n time steps (Eq. 3, forward Euler, Lax-Wendroff).  Asynchronous.
  * One kernel pass per step, or per two steps (mrt_set_steps_per_pass; the
- * default for FP32 storage grids larger than the last-level cache), an odd
+ * default for grids larger than the last-level cache), an odd
  * last step then taking a one-step pass.  Health (NaN, rho <= 0, T <= 0) is
  * recorded on the device and reported by the next synchronising call.
  * Errors: MRT_ESTATE, MRT_EINVAL (n < 0). */
@@ -176,20 +176,20 @@ int mrt_sync(mrt_ctx* ctx);
 int mrt_set_tile(mrt_ctx* ctx, int rows_per_item, int grid_blocks);
 int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
 
-/* Time steps per pass over the populations: 1 or 2 (default: 2 for FP32
- * storage grids whose population buffer exceeds the 256 MB last-level cache,
- * else 1; mrt_autotune times both and keeps the faster).  With 2, one
- * kernel launch advances the state two steps of Eq. 3 (the same per-site
- * arithmetic as two single steps, so the same result up to FP32 rounding
- * order): each work item reads f^n once, keeps f^{n+1} in registers and
- * writes f^{n+2}, recomputing f^{n+1} on the two rows above and below its
- * band of `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = 8 to 32 by grid size)
- * and on its two edge
- * columns, which halves the memory traffic per step.  An odd last step of
- * mrt_step runs the single-step kernel.  FP32 storage forms and the
- * default scheme only (MRT_EINVAL for MRT_FP64; variants set by
- * mrt_set_scheme run one step per pass).  Synchronises.
- * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range, FP64). */
+/* Time steps per pass over the populations: 1 or 2 (default: 2 for grids
+ * whose population buffer exceeds the 256 MB last-level cache, else 1;
+ * mrt_autotune times both and keeps the faster).  With 2, one kernel launch
+ * advances the state two steps of Eq. 3 (the same per-site arithmetic as two
+ * single steps, f^{n+1} rounded to the storage precision as a stored state
+ * would be, so the same result up to rounding order; measured bit-identical):
+ * each work item reads f^n once, keeps f^{n+1} in registers and writes
+ * f^{n+2}, recomputing f^{n+1} on the two rows above and below its band of
+ * `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = 8 to 32 by grid size) and on its
+ * two edge columns, which halves the memory traffic per step.  An odd last
+ * step of mrt_step runs the single-step kernel.  Every precision; the
+ * default scheme only (variants set by mrt_set_scheme run one step per
+ * pass).  Synchronises.
+ * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range). */
 #define MRT_MAX_BAND_ROWS_2 32
 int mrt_set_steps_per_pass(mrt_ctx* ctx, int steps, int rows);
 int mrt_get_steps_per_pass(const mrt_ctx* ctx, int* steps, int* rows);
@@ -214,9 +214,9 @@ int mrt_get_steps_per_pass(const mrt_ctx* ctx, int* steps, int* rows);
 int mrt_set_scheme(mrt_ctx* ctx, int flags);
 
 /* Time candidate launches on the current state (the populations are saved
- * and restored): one-step tiles (rows 1..128, grid sizes) and, for FP32
- * storage, two steps per pass with bands of 8, 16 and 32 rows; keep the
- * fastest per step.  Synchronises. */
+ * and restored): one-step tiles (rows 1..128, grid sizes) and two steps per
+ * pass with bands of 8, 16 and 32 rows; keep the fastest per step.
+ * Synchronises. */
 int mrt_autotune(mrt_ctx* ctx, int steps_per_trial);
 
 void mrt_destroy(mrt_ctx* ctx);
@@ -341,7 +341,7 @@ int mrt_batch_set_tile(mrt_batch* b, int rows_per_item, int grid_blocks);
 int mrt_batch_get_tile(const mrt_batch* b, int* rows_per_item, int* grid_blocks);
 /* As mrt_set_steps_per_pass, for every instance of the batch (default 1;
  * rows 0 = 32, bands never exceed an instance's height).  Synchronises.
- * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range, FP64). */
+ * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range). */
 int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows);
 int mrt_batch_get_steps_per_pass(const mrt_batch* b, int* steps, int* rows);
 int mrt_batch_autotune(mrt_batch* b, int steps_per_trial);

@@ -921,11 +921,15 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
     if (act && !healthy) atomicOr(health, 1u);
 }
 
-// Two blocks (two waves per SIMD) per CU: the occupancy its 213-249 VGPRs
-// (by form) allow; stating it let the compiler schedule for it (measured
-// 1 % faster).
+// FP32 storage: two blocks (two waves per SIMD) per CU, the occupancy its
+// 213-249 VGPRs (by form) allow; stating it let the compiler schedule for it
+// (measured 1 % faster).  FP64 storage holds both register windows in twice
+// the registers (320-370 VGPRs): one block per CU.
+template <typename S>
+constexpr int step2_waves() { return sizeof(S) == 4 ? 2 : 1; }
+
 template <typename S, typename C, bool COMP, bool NT, bool W4>
-__global__ __launch_bounds__(256, 2) void step2_kernel(const Inst* __restrict__ insts,
+__global__ __launch_bounds__(256, (step2_waves<S>())) void step2_kernel(const Inst* __restrict__ insts,
                                                     const Item* __restrict__ items, int nitems,
                                                     const S* __restrict__ fin, S* __restrict__ fout,
                                                     unsigned* __restrict__ health) {
@@ -1519,12 +1523,13 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
     }
 }
 
-// Two steps from fin to fout (FP32 storage forms only; bands of at most
-// kBand2 rows); the reflecting-wall ghosts of fin must be current.  wrap4:
+// Two steps from fin to fout (bands of at most kBand2 rows); the
+// reflecting-wall ghosts of fin must be current.  wrap4:
 // some item is a band that is a whole periodic height of four rows.
 hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                    void* fout, unsigned* health, int grid, bool nt, bool wrap4, hipStream_t st) {
     switch (prec) {
+        case 0: return launch_step2<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
         case 1: return launch_step2<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
         case 2: return launch_step2<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
         default: return hipErrorInvalidValue;
