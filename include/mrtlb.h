@@ -146,8 +146,11 @@ int mrt_step(mrt_ctx* ctx, int n);
  * context's stream); errors as mrt_step. */
 int mrt_prepare_steps(mrt_ctx* ctx, int n);
 
-/* Macroscopic fields of the current populations: rho = fhat_1, u = j/rho,
- * T = (e - rho u^2)/(b rho) (R = 1).  Outputs ny*nx doubles on the host
+/* Macroscopic fields of the current populations: the conserved moments
+ * rho = fhat_1, j = (fhat_2, fhat_3), e = fhat_4 (Appendix rows m1..m4), then
+ * u = j/rho and T = (e - rho u^2)/(b rho) from e = b rho R T + j^2/rho
+ * (definitions under Eqs. 12a-12d) with R = 1 (section "Numerical
+ * simulation").  Outputs ny*nx doubles on the host
  * (on_device = 0; the call synchronises) or on the device (on_device = 1;
  * asynchronous).  Any output pointer may be NULL.
  * Errors: MRT_ESTATE, MRT_EUNSTABLE (health flag set since the last check;
@@ -262,7 +265,10 @@ int mrt_step_checkpointed(mrt_ctx* ctx, void* f, void* f_tmp, int segment, int n
                           void* const* checkpoints);
 
 /* Backward pass over nsteps steps from the checkpoints written by
- * mrt_step_checkpointed (same segment): segment by segment, newest first, it
+ * mrt_step_checkpointed (same segment): the discrete adjoint of nsteps
+ * forward steps of Eq. 3 (forward Euler, Lax-Wendroff), lam^n =
+ * (dF/df^n)^T lam^{n+1} per step as in mrt_adjoint_step, derived from Eq. 3
+ * and the Appendix equilibrium.  Segment by segment, newest first, it
  * recomputes f^start+1 .. f^stop-1 from checkpoint f^start into `work`, then
  * runs mrt_adjoint_step for n = stop-1 down to start.  The checkpointing
  * keeps ceil(N / segment) + segment states for one extra forward step per
@@ -307,9 +313,12 @@ int mrt_init_buffer(mrt_ctx* ctx, const double* rho, const double* ux, const dou
 
 /* -------------------------------------------------------------- batch
  * Many independent grids (e.g. shock tubes of different length, gamma, Pr and
- * Mach) advanced together: every step of every instance runs in one kernel
- * launch over a table of (instance, tile) work items, and mrt_batch_step(n)
- * replays one captured HIP graph of n launches.  Storage precision is the
+ * Mach) advanced together: each instance is the scheme of Eq. 3 with its own
+ * specific-heat ratio (the extra degrees of freedom b, section "Construction"),
+ * its own rates (Pr = s_8/s_6 from Eqs. 12b-12d), grid and boundaries (the
+ * fixed-equilibrium ends of section (b)); every step of every instance runs
+ * in one kernel launch over a table of (instance, tile) work items, and
+ * mrt_batch_step(n) replays one captured HIP graph of n launches.  Storage precision is the
  * batch's; each instance has its own nx, ny, boundary kinds and parameters. */
 typedef struct mrt_instance {
     int nx, ny;

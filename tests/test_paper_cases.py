@@ -97,3 +97,31 @@ def test_paper_riemann2d_quadrant_growth_rates():
     assert g[2] == pytest.approx(1.55e-3, rel=0.05)
     growth = np.exp(g[2] * 12000)
     assert 1e-16 * growth < 1e-6 < 6e-8 * growth
+
+
+def test_sod_with_the_paper_shock_tube_rates_breaks_down():
+    """Why the Sod configuration does not use the paper's strong-shock rates:
+    with s_5 = 5e3, s_6 = 1e4 (section (b)) on the 400-cell Sod tube at
+    dt = 1e-5 the oracle turns non-physical (T < 0 at the contact) after ~330
+    steps, short of the configured 1000; with the rates the Sod workload uses
+    (s_5 = 500, s_6 = 1e3: ten times the viscosity, the paper having run at
+    T = 8-77 where its rates give that much more) it stays physical."""
+    import dataclasses
+
+    from helpers import one_row, oracle_params
+    base = one_row(W.sod_tube())
+
+    def first_bad_step(s, nsteps=1000):
+        c = dataclasses.replace(base, s=s)
+        p = oracle_params(c)
+        f = mrt.init_populations(c.rho, c.ux, c.uy, c.T, p)
+        for n in range(1, nsteps + 1):
+            f = mrt.step(f, p)
+            rho, _, _, T = mrt.macroscopic(f, p.b)
+            if not (np.isfinite(f).all() and rho.min() > 0 and T.min() > 0):
+                return n
+        return None
+
+    bad = first_bad_step(W.rates(5e3, 1e4, 0.71, 1e5))
+    assert bad is not None and 200 < bad < 500, bad
+    assert first_bad_step(base.s) is None
