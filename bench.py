@@ -36,15 +36,15 @@ HEADLINE_TILE_ROWS = 8              # the one-step kernel's band height for this
 # dispatch, mean over the step dispatches) of
 #   bench.py --steps 10 --warmup 2 --no-cpu --no-extra --copy-calibration
 # each scaled by what the same counter reads, in the same run, for a plain
-# 1 GiB device copy (FETCH_SIZE 524,304.9 KiB, WRITE_SIZE 1,048,576 KiB for
+# 1 GiB device copy (FETCH_SIZE 524,305.0 KiB, WRITE_SIZE 1,048,576 KiB for
 # 1,048,576 KiB moved: factors 2.0 and 1.0).  Valid only for the step-kernel
 # sources with this digest and this band height; otherwise the roofline
 # reports traffic = null (comments are not hashed).
 MEASURED_TRAFFIC = {
-    "digest": "fff1c38bb36de48a6e58f4f4240161b48aa58c7cae6d3af67e4ae542ece1cfd3",
+    "digest": "3a9be45849bd141ff3858c0b58676d0478cbc428c6e88bc20257dfe3b7c16cd4",
     "band_rows": HEADLINE_BAND_ROWS,
-    "fetch_kib": 769334.5, "fetch_copy_kib": 524304.9,
-    "write_kib": 1048577.3, "write_copy_kib": 1048576.0,
+    "fetch_kib": 771315.7, "fetch_copy_kib": 524305.0,
+    "write_kib": 1048577.2, "write_copy_kib": 1048576.0,
 }
 STEP_HEADERS = ("mrt_transform.h", "mrt_transform_impl.inc", "mrt_internal.h")
 

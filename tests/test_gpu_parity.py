@@ -150,3 +150,53 @@ def test_fp32_forms_after_1000_steps(precision):
         assert all(err[k] < tol[k] for k in err), (per_pass, err, tol)
         # the stated target itself, separately from the regression bound
         assert all(v < 1e-5 for v in err.values()), (per_pass, err)
+
+
+def _acoustic_front(run, nx, gamma, T):
+    """Section (a)'s sound-speed measurement: a pressure ratio 1 + 1e-10 at
+    equal temperature (fixed-equilibrium tube ends, one periodic row) splits
+    into acoustic fronts; returns the right front's speed relative to
+    sqrt(gamma T) minus one, from the position where the normalised pressure
+    perturbation crosses 1/4 after the front has travelled 0.3."""
+    dx = 1.0 / nx
+    dt = 0.3 * dx / 6.0
+    hi, lo = (1 + 1e-10, 0.0, 0.0, T), (1.0, 0.0, 0.0, T)
+    x = (np.arange(nx) + 0.5) * dx
+    rho = np.where(x < 0.5, 1 + 1e-10, 1.0)[None, :]
+    case = W.Case(f"acoustic_{nx}", nx, 1, rho, 0 * rho, 0 * rho, T + 0 * rho, gamma=gamma, Pr=1.0,
+                  s=W.rates(1 / dt, 1 / dt, 1.0, 1 / dt), dt=dt, dx=dx, dy=dx,
+                  bc=("eq", "eq", "periodic", "periodic"), side_state=(hi, lo, lo, lo), nsteps=0)
+    cs = np.sqrt(gamma * T)
+    n = int(round(0.3 / cs / dt))
+    r, TT = run(case, n)
+    pp = (r[0] * TT[0] - T) / (1e-10 * T)
+    i = np.where(pp > 0.25)[0].max()
+    xf = x[i] + (pp[i] - 0.25) / (pp[i] - pp[i + 1]) * dx
+    return (xf - 0.5) / (n * dt) / cs - 1.0
+
+
+@pytest.mark.parametrize("gamma,T", [(1.4, 1.0), (5.0 / 3.0, 0.5)])
+def test_sound_speed_on_the_gpu(gamma, T):
+    """The sound-speed check of section (a) on the FP64 GPU path: at 400
+    cells the front speed equals the oracle's measurement, and under
+    refinement to 3200 cells it converges to sqrt(gamma T) (its error about
+    halves per refinement: -0.9 %, -0.5 %, ... at 400, 800)."""
+    def gpu(case, n):
+        s = solver_for_case(case, "fp64")
+        s.step(n)
+        rho, ux, uy, TT = s.moments()
+        s.close()
+        return rho, TT
+
+    def cpu(case, n):
+        want, p = oracle_run(case, n)
+        rho, ux, uy, TT = mrt.macroscopic(want, p.b)
+        return rho, TT
+
+    e_cpu = _acoustic_front(cpu, 400, gamma, T)
+    errs = [_acoustic_front(gpu, nx, gamma, T) for nx in (400, 800, 1600, 3200)]
+    print("sound speed: oracle 400", e_cpu, "gpu 400..3200", errs, flush=True)
+    assert abs(errs[0] - e_cpu) < 1e-5
+    for a, b in zip(errs, errs[1:]):
+        assert abs(b) < 0.7 * abs(a)
+    assert abs(errs[-1]) < 0.003
