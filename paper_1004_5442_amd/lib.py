@@ -14,7 +14,9 @@ from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_void_p
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmrtlb.so")
+# the in-tree build; MRTLB_LIBRARY names another build of the same sources
+# (the host-sanitizer test loads one built with address/undefined checks)
+LIB_PATH = os.environ.get("MRTLB_LIBRARY") or os.path.join(HERE, "libmrtlb.so")
 
 MRT_OK, MRT_EINVAL, MRT_EDEVICE, MRT_ESTATE, MRT_EUNSTABLE, MRT_ENOMEM = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "fp32": 1, "fp32_eq64": 2}
