@@ -54,6 +54,31 @@ def test_tube_batch_fp32_matches_oracle(precision):
         assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
 
 
+@pytest.mark.parametrize("rows", [4, 32])
+def test_fp64_two_step_batch_matches_oracle(rows):
+    """FP64 storage, two steps per pass over the mixed batch (13 steps per
+    call over three calls, the last step of each call a one-step pass): every
+    instance against the oracle at 1e-12 of its population scale and against
+    the FP64 one-step batch (<= 1e-15)."""
+    cases = _mixed_cases()
+    one = Batch(cases, "fp64")
+    two = Batch(cases, "fp64")
+    two.set_steps_per_pass(2, rows)
+    assert two.steps_per_pass() == (2, rows)
+    for call in range(3):
+        print(f"call {call} fp64 rows {rows}", flush=True)
+        one.step(13)
+        two.step(13)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 39)
+        got = two.populations(i)
+        err = float(np.max(np.abs(got - want)) / np.abs(want).max())
+        d = float(np.max(np.abs(got - one.populations(i))) / np.abs(want).max())
+        print(c.name, "vs oracle", err, "vs one step", d, flush=True)
+        assert err <= 1e-12, (c.name, err)
+        assert d <= 1e-15, (c.name, d)
+
+
 @pytest.mark.parametrize("precision,rows", [("fp32_eq64", 4), ("fp32_eq64", 32), ("fp32", 4)])
 def test_two_step_batch_matches_oracle_and_single_step(precision, rows):
     """Two steps per pass over the mixed batch (ragged sizes, every
