@@ -252,10 +252,12 @@ hipError_t run_graphs(GraphCache& cache, int& cur, int n, hipStream_t stream, En
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         if (graph) (void)hipGraphDestroy(graph);
         (void)hipStreamDestroy(cap);
-        // upload the executable graph to the device now, so that its first
-        // replay (inside a caller's timed region or latency-critical loop)
-        // does not carry the one-time upload
-        if (e == hipSuccess) e = hipGraphUpload(exec, stream);
+        // when only preparing (mrt_prepare_steps), upload the executable
+        // graph to the device now, so that its first replay (inside a
+        // caller's timed region or latency-critical loop) does not carry the
+        // one-time upload; a graph made by a launching call is uploaded by
+        // its launch (which also works while the caller captures the stream)
+        if (e == hipSuccess && !launch) e = hipGraphUpload(exec, stream);
         if (e != hipSuccess) {
             if (exec) (void)hipGraphExecDestroy(exec);
             return e;
