@@ -184,7 +184,8 @@ int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
  * mrt_autotune times both and keeps the faster).  With 2, one kernel launch
  * advances the state two steps of Eq. 3 (the same per-site arithmetic as two
  * single steps, f^{n+1} rounded to the storage precision as a stored state
- * would be, so the same result up to rounding order; measured bit-identical):
+ * would be, so the same result up to rounding order: measured bit-identical
+ * in the FP32 storage forms, within a few roundings in FP64):
  * each work item reads f^n once, keeps f^{n+1} in registers and writes
  * f^{n+2}, recomputing f^{n+1} on the two rows above and below its band of
  * `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = 8 to 32 by grid size) and on its

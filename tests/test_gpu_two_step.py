@@ -75,8 +75,10 @@ def test_two_step_matches_oracle_and_single_step(bc, shape, rows):
 def test_fp64_two_step_matches_oracle_and_single_step(bc, shape, rows):
     """FP64 storage, two steps per pass (one block per CU: both register
     windows in FP64): populations after 13 steps against the oracle at
-    1e-12 of their scale, and against the FP64 one-step kernel (the same
-    site arithmetic, f^{n+1} held as the double a stored state would be)."""
+    1e-12 of their scale, and against the FP64 one-step kernel to rounding
+    order (1e-13: the same site arithmetic, f^{n+1} held as the double a
+    stored state would be, the FP64 collision's FMA fusion possibly chosen
+    differently per unrolled row)."""
     nx, ny = shape
     nsteps = 13
     case = smooth_case(nx, ny, bc, seed=3 * nx + ny)
@@ -93,7 +95,7 @@ def test_fp64_two_step_matches_oracle_and_single_step(bc, shape, rows):
     d = close_to_single_step(got, one.populations())
     print("vs oracle", err, "vs single step", d, flush=True)
     assert err <= 1e-12, err
-    assert d <= 1e-15, d
+    assert d <= 1e-13, d
     one.close()
     two.close()
 
