@@ -255,9 +255,10 @@ int mrt_adjoint_step_noalloc(mrt_ctx* ctx, const void* lam_next, const void* f_n
                              double* ds);
 
 /* Forward pass that keeps sqrt(N)-style checkpoints for a later
- * mrt_adjoint_sweep: for n = 0 .. nsteps-1, copies f^n into
- * checkpoints[n / segment] when n % segment == 0, then steps (as
- * mrt_step_buffers).  f: on entry f^0, on return f^nsteps.  f_tmp: one more
+ * mrt_adjoint_sweep: checkpoints[k] receives f^(k * segment) for
+ * k * segment < nsteps (f^0 by a copy, the others written there by their
+ * step directly), stepping as mrt_step_buffers.  segment = 1 keeps every
+ * state (no recomputation in the sweep).  f: on entry f^0, on return f^nsteps.  f_tmp: one more
  * state buffer (overwritten).  checkpoints: ceil(nsteps / segment) buffers.
  * All device buffers in the storage precision and padded layout, owned by the
  * caller and distinct.  MRT_EINVAL on NULL or aliased buffers, segment < 1 or

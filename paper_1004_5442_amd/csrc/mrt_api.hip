@@ -999,14 +999,21 @@ int mrt_step_checkpointed(mrt_ctx* c, void* f, void* f_tmp, int segment, int nst
         if (!checkpoints[k] || checkpoints[k] == f || checkpoints[k] == f_tmp)
             return ctx_fail(c, MRT_EINVAL, "checkpoint buffers must be distinct from f and f_tmp");
     const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));
+    if (nsteps == 0) return MRT_OK;
+    // f^0 is copied into the first checkpoint; every later checkpointed
+    // state is written there by its step directly (no copy), the others go
+    // to whichever of f / f_tmp the step does not read
+    HIPTRY(hipMemcpyAsync(checkpoints[0], f, bytes, hipMemcpyDeviceToDevice, c->stream));
     void* a = f;
-    void* b = f_tmp;
     for (int n = 0; n < nsteps; ++n) {
-        if (n % segment == 0)
-            HIPTRY(hipMemcpyAsync(checkpoints[n / segment], a, bytes, hipMemcpyDeviceToDevice, c->stream));
-        const int rc = mrt_step_buffers(c, a, b);
+        void* dst;
+        if ((n + 1) % segment == 0 && n + 1 < nsteps)
+            dst = checkpoints[(n + 1) / segment];
+        else
+            dst = a == f ? f_tmp : f;
+        const int rc = mrt_step_buffers(c, a, dst);
         if (rc != MRT_OK) return rc;
-        std::swap(a, b);
+        a = dst;
     }
     if (a != f) HIPTRY(hipMemcpyAsync(f, a, bytes, hipMemcpyDeviceToDevice, c->stream));
     return MRT_OK;

@@ -139,7 +139,7 @@ def test_checkpoint_segment_does_not_change_gradient():
     assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[1], grads[2])
 
 
-@pytest.mark.parametrize("nsteps,segment", [(13, 4), (12, 4), (5, 9), (1, 1)])
+@pytest.mark.parametrize("nsteps,segment", [(13, 4), (12, 4), (5, 9), (1, 1), (7, 1), (8, 2)])
 def test_native_checkpoint_loops_equal_explicit_steps(nsteps, segment):
     """mrt_step_checkpointed / mrt_adjoint_sweep against the same work done
     one mrt_step_buffers / mrt_adjoint_step call at a time (states and lam
