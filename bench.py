@@ -480,6 +480,25 @@ def extra_legs(head, prec, steps):
                     "note": "36,000 cells: launch-latency bound (captured graphs of 64 steps)"}
         return run
 
+    def paper_riemann2d():
+        # section (c)'s own problem at its printed size (500^2, FP64 MRT):
+        # cache-resident, effective bandwidth
+        c = W.paper_riemann2d()
+        rr = time_solver(c, "fp64", 4 * k, 5)
+        rr["steps"] = 4 * k
+        return {"mlups": round(rr["mlups"], 1), "steps_per_pass": rr["per_pass"],
+                "effective_GBs": roofline(c, "fp64", rr)["achieved"],
+                "note": "fits the 256 MB Infinity Cache: effective, not HBM, bandwidth"}
+
+    def strong_shock():
+        # section (b)'s strong-shock tube (1100 x 1, FP64 MRT, dt = 1e-6):
+        # launch-latency bound
+        c = W.strong_shock_tube(1.4, False)
+        rr = time_solver(c, "fp64", 16 * k, 64)
+        return {"mlups": round(rr["mlups"], 1), "ms_per_step": round(rr["ms_per_step"], 5),
+                "steps_for_t_0.13_s": round(c.nsteps * rr["ms_per_step"] / 1e3, 3),
+                "note": "1,100 cells: launch-latency bound (captured graphs of 64 steps)"}
+
     return {
         "fp32_eq64_one_step_per_pass": one_step,
         "fp64_same_grid": fp64,
@@ -490,6 +509,8 @@ def extra_legs(head, prec, steps):
         "scheme_variants_4096_fp32_eq64": variants,
         "rm_instability_360x100_fp32_eq64": rm("fp32_eq64"),
         "rm_instability_360x100_fp64": rm("fp64"),
+        "paper_riemann2d_500_fp64": paper_riemann2d,
+        "strong_shock_tube_1100_fp64": strong_shock,
         "batched_512_tubes": lambda: time_batch(max(50, steps // 2), 5),
         "adjoint_256": lambda: time_adjoint(100),
         "adjoint_2048": lambda: time_adjoint_large(2048, 20),
