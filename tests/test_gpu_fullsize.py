@@ -8,7 +8,8 @@ Riemann grid (cache-resident, cached stores) run a few steps on the GPU; the
 oracle evaluates small windows around sampled cells (the shock front, the
 bubble edge, every kind of boundary, the corners) one by one
 (``mrt.evolve_window``: a window of the initial fields grown by one cell per
-step, so every sampled cell's dependence cone is inside it).  A longer run
+step, so every sampled cell's dependence cone is inside it); both grids
+again after 100 steps against 206 x 206 windows.  A longer run
 checks a property that holds at any size: the shock-bubble problem is
 mirror-symmetric about y = 1/2, so the GPU fields must be too, to rounding.
 """
@@ -135,6 +136,79 @@ def test_riemann2d_1024_sampled_autotuned(precision):
     centres = [(c, c), (c - 1, c + 1), (c, 0), (c, n - 1), (0, c), (n - 1, c),
                (0, 0), (n - 1, n - 1), (255, 700), (768, 300)]
     compare(case, s, centres, NSTEPS, precision)
+    s.close()
+
+
+_WINDOWS = {}
+
+
+def _oracle_windows(case, centres, nsteps):
+    """The oracle's patches after nsteps steps, each evolved on its own
+    window grown by nsteps cells (cached per case name and step count)."""
+    key = (case.name, nsteps, tuple(centres))
+    if key not in _WINDOWS:
+        p = oracle_params(case)
+        _WINDOWS[key] = [oracle_patch(case, p, patch, nsteps) for patch in patches(case, centres)]
+    return _WINDOWS[key]
+
+
+def compare_long(case, solver, centres, nsteps, precision):
+    """As compare, after a longer run: FP64 populations at 1e-12 of their
+    scale, the FP32 forms' fields at the stated 1e-5."""
+    p = oracle_params(case)
+    want = np.concatenate(_oracle_windows(case, centres, nsteps), axis=2)
+    got_all = []
+    for x0, x1, y0, y1 in patches(case, centres):
+        yy, xx = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+        got_all.append(device_samples(solver, xx.ravel(), yy.ravel()).reshape(16, PATCH, PATCH))
+    got = np.concatenate(got_all, axis=2)
+    if precision == "fp64":
+        err = np.max(np.abs(got - want)) / np.abs(want).max()
+        print(case.name, precision, nsteps, "steps: population error", err, flush=True)
+        assert err <= 1e-12
+    else:
+        err = field_errors(mrt.macroscopic(got, p.b), mrt.macroscopic(want, p.b))
+        print(case.name, precision, nsteps, "steps:", err, flush=True)
+        assert max(err.values()) < 1e-5, err
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_eq64", "fp32"])
+def test_riemann2d_1024_sampled_after_100_steps(precision):
+    """The 2D Riemann workload at its configured size in its autotuned
+    launch, after 100 steps, on patches where all four states meet, on a
+    quadrant interface, and where interfaces meet two outflow sides, against
+    the oracle's windowed evaluation (windows of up to 206 x 206 cells)."""
+    n, nsteps = 1024, 100
+    case = W.riemann2d(n=n, seed=0)
+    print(f"case {case.name} {precision} autotuned, {nsteps} steps", flush=True)
+    s = solver_for_case(case, precision)
+    s.autotune(4)
+    s.step(nsteps)
+    s.sync()
+    c = n // 2
+    compare_long(case, s, [(c, c), (c, 300), (0, c), (c, n - 1)], nsteps, precision)
+    s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_eq64"])
+def test_shock_bubble_4096_sampled_after_100_steps(precision):
+    """The shock-bubble workload at 4096^2 in the launch the benchmark times
+    for both precisions (two steps per pass, 32-row bands), after 100 steps,
+    on patches at the shock front, where it meets a wall, on the bubble edge
+    and at the inflow and outflow sides, against the oracle's windowed
+    evaluation (windows of up to 206 x 206 cells)."""
+    n, nsteps = 4096, 100
+    case = W.shock_bubble(n=n)
+    print(f"case {case.name} {precision} two steps per pass, {nsteps} steps", flush=True)
+    s = solver_for_case(case, precision)
+    s.set_steps_per_pass(2, HEADLINE_BAND_ROWS_2)
+    assert s.steps_per_pass() == (2, HEADLINE_BAND_ROWS_2)
+    s.step(nsteps)
+    s.sync()
+    bx, by, br = int(0.25 * n), n // 2, int(0.1 * n)
+    centres = [(int(0.1 * n) + 8, n // 2), (int(0.1 * n) + 8, 1), (bx - br, by), (bx, by + br),
+               (0, n // 3), (n - 1, 2 * n // 3)]
+    compare_long(case, s, centres, nsteps, precision)
     s.close()
 
 
