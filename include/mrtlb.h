@@ -369,12 +369,17 @@ const char* mrt_batch_last_error(const mrt_batch* b);
  *  mrt_host_collision: out = dt Minv diag(s) (M f - fhat^eq)   (Eq. 3).
  *  mrt_host_cell_adjoint: coll = dt (dC/df)^T lam at one cell, and
  *    dsk[k] = dt (fhat_k - fhat^eq_k)(Minv^T lam)_k.
- * Arrays are 16 doubles; s holds s_1..s_16.  MRT_EINVAL on NULL or gamma<=1. */
+ * Arrays are 16 doubles; s holds s_1..s_16.  MRT_EINVAL on NULL or gamma<=1.
+ *  mrt_host_conserved_fp32: the conserved moments (rho, jx, jy, e; rows
+ *    m1..m4 of the Appendix matrix) of 16 FP32 populations f as the MRT_FP32
+ *    form computes them, compensated FP32 sums within one unit in the last
+ *    place of the exact sums; q receives 4 floats.  MRT_EINVAL on NULL. */
 int mrt_host_transform(int which, const double* in, double* out);
 int mrt_host_equilibrium(double gamma, double rho, double ux, double uy, double T, double* f);
 int mrt_host_collision(double gamma, const double* s, double dt, const double* f, double* out);
 int mrt_host_cell_adjoint(double gamma, const double* s, double dt, const double* f,
                           const double* lam, double* coll, double* dsk);
+int mrt_host_conserved_fp32(const float* f, float* q);
 
 #ifdef __cplusplus
 }

@@ -1541,4 +1541,10 @@ int mrt_host_cell_adjoint(double gamma, const double* s, double dt, const double
     return MRT_OK;
 }
 
+int mrt_host_conserved_fp32(const float* f, float* q) {
+    if (!f || !q) return MRT_EINVAL;
+    mrt::conserved_compensated(f, q);
+    return MRT_OK;
+}
+
 }  // extern "C"

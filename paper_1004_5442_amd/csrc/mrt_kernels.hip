@@ -80,37 +80,9 @@ __device__ __forceinline__ void no_value(S (&h)[16]) {
 constexpr bool moves_x(int i) { return i < 8 ? (i & 1) == 0 : true; }
 constexpr bool moves_y(int i) { return i < 8 ? (i & 1) == 1 : true; }
 
-// Conserved moments as compensated FP32 sums over the 16 populations:
-// rho = sum f, j = sum v f, e = sum (v^2 + eta^2) f.  Each addition's
-// rounding error is recovered exactly by Knuth's branch-free TwoSum (the same
-// error Neumaier's ordered form recovers, without its compare and select)
-// and accumulated in c.
-__device__ __forceinline__ void neumaier(float& s, float& c, float x) {
-    MRT_CONTRACT_IN_EXPRESSIONS
-    const float t = s + x;
-    const float bp = t - s, ap = t - bp;
-    c += (s - ap) + (x - bp);
-    s = t;
-}
-__device__ __forceinline__ void conserved_compensated(const float f[16], float q[4]) {
-    MRT_CONTRACT_IN_EXPRESSIONS
-    const float sp[4] = {1.0f, 6.0f, float(kR2), float(kR32)};
-    const float eps[4] = {7.25f, 36.0f, 4.0f, 9.0f};
-    float s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int k = i >> 2;
-        neumaier(s[0], c[0], f[i]);
-        if (sgn_x(i) != 0) neumaier(s[1], c[1], float(sgn_x(i)) * sp[k] * f[i]);
-        if (sgn_y(i) != 0) neumaier(s[2], c[2], float(sgn_y(i)) * sp[k] * f[i]);
-        neumaier(s[3], c[3], eps[k] * f[i]);
-    }
-#pragma unroll
-    for (int m = 0; m < 4; ++m) q[m] = s[m] + c[m];
-}
-
 // dt * C for one cell in precision C (see collision_dt), converted to the
-// storage type; COMP replaces the conserved moments by compensated FP32 sums.
+// storage type; COMP replaces the conserved moments by compensated FP32 sums
+// (conserved_compensated, mrt_transform.h).
 template <typename C, bool COMP, typename S, typename DP>
 __device__ __forceinline__ void cell_collision(const S fs[16], C b, C binv, DP sdt,
                                                S out[16], C& rho, C& P) {

@@ -96,4 +96,96 @@ MRT_DISPATCH(collision_dt, (const C f[16], C b, const C sdt[16], C out[16], C& r
              (f, b, sdt, out, rho, P))
 #undef MRT_DISPATCH
 
+// ---------------------------------------------- compensated FP32 moments
+// The conserved moments rho = sum f, j = sum v f, e = sum (|v|^2 + eta^2) f
+// (rows m1..m4 of M) of FP32 populations as compensated FP32 sums, for the
+// all-FP32 form.  The sums follow the butterfly of pops_to_moments (shell
+// sums, signed x and y sums, then the four shells combined), and every
+// addition and product on that path is an error-free transformation: the
+// rounded result plus its exact rounding error (Knuth's branch-free TwoSum;
+// the product's error from one FMA).  The errors are added up in plain FP32
+// and added to the rounded sum once, so the result is within one unit in the
+// last place of the exact sum of the FP32 terms (the velocity and eta^2
+// constants as FP32 values), and in nearly every case the correctly rounded
+// value.  Following the butterfly shares its rounded sums with the moment
+// transform and costs about 260 instructions per cell (one TwoSum per
+// addend into four running sums took about 430).
+
+// a + b = s + e exactly (round to nearest, no overflow), any magnitudes.
+MRT_HD float two_sum(float a, float b, float& e) {
+    MRT_CONTRACT_IN_EXPRESSIONS
+    const float s = a + b;
+    const float bp = s - a;
+    const float ap = s - bp;
+    e = (a - ap) + (b - bp);
+    return s;
+}
+// a * b = p + e exactly (no overflow or underflow).
+MRT_HD float two_prod(float a, float b, float& e) {
+    MRT_CONTRACT_IN_EXPRESSIONS
+    const float p = a * b;
+    e = __builtin_fmaf(a, b, -p);
+    return p;
+}
+
+MRT_HD void conserved_compensated(const float f[16], float q[4]) {
+    MRT_CONTRACT_IN_EXPRESSIONS
+    float sg[4], esg[4], X[4], eX[4], Y[4], eY[4];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {           // axis shells: (+x, +y, -x, -y)
+        const float a0 = f[4 * k], a1 = f[4 * k + 1], a2 = f[4 * k + 2], a3 = f[4 * k + 3];
+        float e1, e2, e3;
+        const float px = two_sum(a0, a2, e1), py = two_sum(a1, a3, e2);
+        sg[k] = two_sum(px, py, e3);
+        esg[k] = (e1 + e2) + e3;
+        X[k] = two_sum(a0, -a2, eX[k]);
+        Y[k] = two_sum(a1, -a3, eY[k]);
+    }
+#pragma unroll
+    for (int k = 2; k < 4; ++k) {           // diagonal shells: (++, -+, --, +-)
+        const float d0 = f[4 * k], d1 = f[4 * k + 1], d2 = f[4 * k + 2], d3 = f[4 * k + 3];
+        float e1, e2, e3, e4, e5, e6, e7;
+        const float p02 = two_sum(d0, d2, e1), p13 = two_sum(d1, d3, e2);
+        sg[k] = two_sum(p02, p13, e3);
+        esg[k] = (e1 + e2) + e3;
+        const float m02 = two_sum(d0, -d2, e4), m31 = two_sum(d3, -d1, e5);
+        X[k] = two_sum(m02, m31, e6);
+        eX[k] = (e4 + e5) + e6;
+        Y[k] = two_sum(m02, -m31, e7);
+        eY[k] = (e4 - e5) + e7;
+    }
+    {   // rho = sum of the shell sums
+        float r1, r2, r3;
+        const float a = two_sum(sg[0], sg[1], r1), b = two_sum(sg[2], sg[3], r2);
+        const float s = two_sum(a, b, r3);
+        q[0] = s + (((esg[0] + esg[1]) + (esg[2] + esg[3])) + ((r1 + r2) + r3));
+    }
+    // j = X_1 + 6 X_2 + sqrt 2 X_3 + (3 / sqrt 2) X_4 (and Y): the x speeds of the shells
+    const float sp1 = 6.0f, sp2 = float(kR2), sp3 = float(kR32);
+    const float* odd[2] = {X, Y};
+    const float* eodd[2] = {eX, eY};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const float* v = odd[a];
+        const float* ev = eodd[a];
+        float p1, p2, p3, r1, r2, r3;
+        const float t1 = two_prod(sp1, v[1], p1), t2 = two_prod(sp2, v[2], p2),
+                    t3 = two_prod(sp3, v[3], p3);
+        const float u = two_sum(v[0], t1, r1), w = two_sum(t2, t3, r2);
+        const float s = two_sum(u, w, r3);
+        q[1 + a] = s + (((ev[0] + sp1 * ev[1]) + (sp2 * ev[2] + sp3 * ev[3])) + ((p1 + p2) + p3)
+                        + ((r1 + r2) + r3));
+    }
+    {   // e = 7.25 sg_1 + 36 sg_2 + 4 sg_3 + 9 sg_4  (|v|^2 + eta^2 per shell)
+        float p0, p1, p3, r1, r2, r3;
+        const float t0 = two_prod(7.25f, sg[0], p0), t1 = two_prod(36.0f, sg[1], p1);
+        const float t2 = 4.0f * sg[2];      // exact
+        const float t3 = two_prod(9.0f, sg[3], p3);
+        const float u = two_sum(t0, t1, r1), w = two_sum(t2, t3, r2);
+        const float s = two_sum(u, w, r3);
+        q[3] = s + (((7.25f * esg[0] + 36.0f * esg[1]) + (4.0f * esg[2] + 9.0f * esg[3]))
+                    + ((p0 + p1) + p3) + ((r1 + r2) + r3));
+    }
+}
+
 }  // namespace mrt

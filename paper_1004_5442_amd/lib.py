@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, byref, c_double, c_int, c_longlong, c_void_p
+from ctypes import POINTER, byref, c_double, c_float, c_int, c_longlong, c_void_p
 
 import numpy as np
 
@@ -51,6 +51,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 _D = POINTER(c_double)
+_F = POINTER(c_float)
 _proto = {
     "mrt_init_grid": (c_int, [POINTER(c_void_p), c_int, c_int, c_int, POINTER(c_int), POINTER(c_void_p), c_void_p]),
     "mrt_population_bytes": (c_longlong, [c_int, c_int, c_int]),
@@ -100,6 +101,7 @@ _proto = {
     "mrt_host_equilibrium": (c_int, [c_double, c_double, c_double, c_double, c_double, _D]),
     "mrt_host_collision": (c_int, [c_double, _D, c_double, _D, _D]),
     "mrt_host_cell_adjoint": (c_int, [c_double, _D, c_double, _D, _D, _D, _D]),
+    "mrt_host_conserved_fp32": (c_int, [_F, _F]),
 }
 for _name, (_res, _args) in _proto.items():
     _fn = getattr(_lib, _name)
@@ -172,3 +174,12 @@ def host_cell_adjoint(gamma, s, dt, f, lam):
     coll, dsk = np.empty(16), np.empty(16)
     check(_lib.mrt_host_cell_adjoint(gamma, _dptr(s), dt, _dptr(f), _dptr(lam), _dptr(coll), _dptr(dsk)))
     return coll, dsk
+
+
+def host_conserved_fp32(f):
+    """(rho, jx, jy, e) of 16 FP32 populations as the all-FP32 form computes
+    them (compensated FP32 sums)."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    q = np.empty(4, dtype=np.float32)
+    check(_lib.mrt_host_conserved_fp32(f.ctypes.data_as(_F), q.ctypes.data_as(_F)))
+    return q

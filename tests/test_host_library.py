@@ -83,3 +83,58 @@ def test_cell_adjoint_matches_complex_step_jacobian():
         _, ds = oadj.adjoint_step(lam.reshape(16, 1, 1), f.reshape(16, 1, 1),
                                   mrt.Params(gamma=gamma, s=s, dt=dt, dx=1.0, dy=1.0))
         np.testing.assert_allclose(-dsk, ds, rtol=0, atol=1e-11 * np.abs(ds).max())
+
+
+def _fp32_conserved_exact(f32):
+    """Exact rational rho, jx, jy, e of FP32 populations with the FP32 values
+    of the Appendix rows m1..m4 (the oracle's dense matrix)."""
+    from fractions import Fraction
+    M = mrt.transformation_matrix()
+    F = [Fraction(float(x)) for x in f32]
+    return [sum(Fraction(float(np.float32(M[r, i]))) * F[i] for i in range(16)) for r in range(4)]
+
+
+def _fp32_cases(rng, n):
+    for _ in range(n):
+        gamma = 1 + rng.uniform(0.05, 1.0)
+        b = mrt.b_from_gamma(gamma)
+        state = (rng.uniform(0.1, 10), rng.uniform(-3, 3), rng.uniform(-3, 3), rng.uniform(0.1, 2))
+        f = np.asarray(mrt.feq(*state, b), dtype=np.float64)
+        yield "equilibrium", f.astype(np.float32)
+        yield "perturbed", (f * (1 + 1e-3 * rng.standard_normal(16))).astype(np.float32)
+        # signs and magnitudes over nine decades
+        yield "wide", (rng.choice([-1.0, 1.0], 16) * 10.0 ** rng.uniform(-6, 3, 16)).astype(np.float32)
+        # opposite populations nearly equal: the momenta cancel
+        c = rng.uniform(0.1, 1, 16)
+        c[2::4] = c[0::4] * (1 + 1e-6 * rng.standard_normal(4))
+        c[3::4] = c[1::4] * (1 + 1e-6 * rng.standard_normal(4))
+        yield "cancelling", c.astype(np.float32)
+
+
+def test_fp32_conserved_sums_are_correctly_rounded():
+    """The all-FP32 form's compensated conserved moments against exact
+    rational sums of the same FP32 terms: within one unit in the last place
+    always (the error-free transformations' bound) and the correctly rounded
+    value in nearly every case, on equilibria, perturbed equilibria,
+    cancelling momenta and terms over nine decades.  Plain FP32 sums of the
+    same terms miss the correctly rounded value often, so the bound is a
+    test of the compensation."""
+    rng = np.random.default_rng(11)
+    M = mrt.transformation_matrix()
+    M32 = M[:4].astype(np.float32)
+    hits = plain_hits = total = 0
+    for kind, f in _fp32_cases(rng, 300):
+        got = lib.host_conserved_fp32(f)
+        plain = np.zeros(4, dtype=np.float32)
+        for i in range(16):
+            plain = plain + M32[:, i] * f[i]
+        for r, ex in enumerate(_fp32_conserved_exact(f)):
+            rounded = np.float32(float(ex))
+            ulp = float(np.spacing(np.abs(rounded)))
+            assert abs(float(got[r]) - float(ex)) <= ulp, (kind, r, got[r], float(ex))
+            hits += got[r] == rounded
+            plain_hits += plain[r] == rounded
+            total += 1
+    print("correctly rounded:", hits, "of", total, "; plain FP32 sums:", plain_hits)
+    assert hits >= 0.999 * total
+    assert plain_hits < 0.9 * total
