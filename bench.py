@@ -184,7 +184,9 @@ def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, sche
 
 def time_batch(steps, warmup):
     """The batched form: 512 seeded shock tubes (nx 200..4000, ny 4), FP32
-    populations with FP64 collision, graph-captured steps."""
+    populations with FP64 collision, graph-captured passes in the launch the
+    batch autotuner picks (the tube march, four steps per pass, on this
+    batch); the step counts are rounded up to whole passes."""
     import torch
 
     from paper_1004_5442_amd import workloads as W
@@ -199,6 +201,7 @@ def time_batch(steps, warmup):
     pre = _preheat(heat.step, max_steps=cases[0].nsteps)
     heat.close()
     del heat
+    steps, warmup = -(-steps // k) * k, -(-warmup // k) * k
     b.step(warmup)
     b.prepare(steps)
     torch.cuda.synchronize()
@@ -209,7 +212,8 @@ def time_batch(steps, warmup):
     pp = b.steps_per_pass()
     b.close()
     return {"mlups": round(cells * steps / sec / 1e6, 1), "cells": cells, "instances": len(cases),
-            "ms_per_step": round(1e3 * sec / steps, 4), "tile_rows": tile[0],
+            "ms_per_step": round(1e3 * sec / steps, 4), "steps": steps, "tile_rows": tile[0],
+            "kernel": {1: "step_kernel", 2: "step2_kernel", 4: "tube_kernel"}[pp[0]],
             "steps_per_pass": pp[0], "band_rows": pp[1], "preheat_steps": pre,
             "roofline_frac": round(cells * 128 * steps / sec / 1e9 / HBM_PEAK_GBS, 4)}
 

@@ -345,14 +345,22 @@ int mrt_batch_read_moments(mrt_batch* b, int i, double* rho, double* ux, double*
 int mrt_batch_get_populations(mrt_batch* b, int i, double* f);
 /* Rows per work item of the one-step kernel (each work item is 256 columns
  * of one instance, one 4-wave workgroup) and workgroups launched (0 = one
- * per work item); autotune times candidates, one and two steps per pass, on
- * the current state (saved and restored) and keeps the fastest.  Changing
- * the tile drops the captured graphs. */
+ * per work item); autotune times candidates, one, two and (where allowed)
+ * four steps per pass, on the current state (saved and restored) and keeps
+ * the fastest.  Changing the tile drops the captured graphs. */
 int mrt_batch_set_tile(mrt_batch* b, int rows_per_item, int grid_blocks);
 int mrt_batch_get_tile(const mrt_batch* b, int* rows_per_item, int* grid_blocks);
 /* As mrt_set_steps_per_pass, for every instance of the batch (default 1;
- * rows 0 = 32, bands never exceed an instance's height).  Synchronises.
- * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range). */
+ * rows 0 = 32, bands never exceed an instance's height).  steps = 4: the
+ * tube march, for batches whose every instance has four periodic rows and
+ * fixed-equilibrium x sides (the shock tubes of section (b)) in FP32
+ * storage: one pass advances a tube four steps (Eq. 3 each), each block
+ * holding all four rows in registers and storing 248 of the 256 columns it
+ * computes; rows is ignored; a step count that is not a multiple of four
+ * ends with single steps.  Results equal four single steps to rounding
+ * order (bit for bit in MRT_FP32).  Synchronises.
+ * Errors: MRT_EINVAL (steps not 1, 2 or 4; rows out of range; 4 on a batch
+ * the tube march does not cover). */
 int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows);
 int mrt_batch_get_steps_per_pass(const mrt_batch* b, int* steps, int* rows);
 int mrt_batch_autotune(mrt_batch* b, int steps_per_trial);

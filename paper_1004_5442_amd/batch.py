@@ -73,7 +73,9 @@ class Batch:
         return r.value, g.value
 
     def set_steps_per_pass(self, steps: int, rows: int = 0):
-        """1 or 2 time steps per kernel pass (mrt_batch_set_steps_per_pass)."""
+        """1, 2 or 4 time steps per kernel pass (mrt_batch_set_steps_per_pass;
+        4: the tube march, for four-row periodic tubes with fixed-equilibrium
+        x sides in FP32 storage)."""
         self._check(L.raw().mrt_batch_set_steps_per_pass(self._h, int(steps), int(rows)))
 
     def steps_per_pass(self):

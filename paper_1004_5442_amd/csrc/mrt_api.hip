@@ -17,6 +17,7 @@
 
 #include "mrt_dual.h"
 #include "mrt_internal.h"
+#include "mrt_tube.h"
 #include "../../include/mrtlb.h"
 
 namespace mrt {
@@ -26,6 +27,8 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
                   void* fout, unsigned* health, int grid, bool nt, bool walls, hipStream_t st);
 hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                    void* fout, unsigned* health, int grid, bool nt, bool wrap4, hipStream_t st);
+hipError_t k_tube(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
+                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
 hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool reflect,
                      const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
@@ -50,6 +53,8 @@ hipError_t k_import(int prec, const Inst* P, long long cells, const double* in, 
 
 using mrt::Inst;
 using mrt::Item;
+using mrt::kTubeSteps;
+using mrt::kTubeWidth;
 
 // Scratch of mrt_adjoint_step_noalloc: the rate-gradient partial rows of one
 // adjoint step (one row of 16 doubles per work item, then the reduction's 64
@@ -1129,6 +1134,9 @@ struct mrt_batch {
     int nitems2 = 0, rows2 = 0;
     bool wrap4 = false;                     // some band is a whole periodic height of 4 rows
     GraphCache graphs2;                     // captured two-step passes
+    Item* d_items4 = nullptr;               // work items of the tube march
+    int nitems4 = 0;
+    GraphCache graphs4;                     // captured tube-march passes
     std::string err;
 };
 
@@ -1167,6 +1175,33 @@ int batch_items2(mrt_batch* b, int rows) {
     b->wrap4 = false;
     for (int i = 0; i < b->count; ++i) b->wrap4 = b->wrap4 || wraps_four_rows(b->insts[i], rows);
     b->graphs2.clear();
+    return MRT_OK;
+}
+
+// Whether the tube march (kTubeSteps steps per pass) can advance the
+// batch: FP32 storage, and every instance four periodic rows with
+// fixed-equilibrium x sides.
+bool tube_march_ok(const mrt_batch* b) {
+    if (b->prec == MRT_FP64) return false;
+    for (const Inst& I : b->insts)
+        if (I.ny != 4 || I.bc[2] != MRT_BC_PERIODIC || I.bc[3] != MRT_BC_PERIODIC ||
+            I.bc[0] != MRT_BC_EQ || I.bc[1] != MRT_BC_EQ)
+            return false;
+    return true;
+}
+
+// Work items of the tube march: kTubeWidth-column chunks of each instance.
+int batch_items4(mrt_batch* b) {
+    std::string& ctx_err = b->err;
+    std::vector<Item> items;
+    for (int i = 0; i < b->count; ++i)
+        for (int x0 = 0; x0 < b->insts[i].nx; x0 += kTubeWidth) items.push_back(Item{i, x0, 0, 4});
+    if (b->d_items4) HIPTRY(hipFree(b->d_items4));
+    b->d_items4 = nullptr;
+    HIPTRY(hipMalloc(&b->d_items4, items.size() * sizeof(Item)));
+    HIPTRY(hipMemcpy(b->d_items4, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    b->nitems4 = int(items.size());
+    b->graphs4.clear();
     return MRT_OK;
 }
 
@@ -1276,6 +1311,24 @@ static int batch_step_impl(mrt_batch* b, int n, bool launch) {
     if (!b || n < 0) return MRT_EINVAL;
     std::string& ctx_err = b->err;
     if (n == 0) return MRT_OK;
+    if (b->per_pass == kTubeSteps) {
+        // the tube march (no reflecting sides: its x sides are fixed
+        // equilibria, its y sides periodic), the remaining steps one by one
+        auto enqueue4 = [&](int cur, hipStream_t st) -> hipError_t {
+            return mrt::k_tube(b->prec, b->d_insts, b->d_items4, b->nitems4, b->f[cur], b->f[1 - cur],
+                               b->d_health, 0, b->nt, st);
+        };
+        const int passes = n / kTubeSteps;
+        if (passes > 0) HIPTRY(run_graphs(b->graphs4, b->cur, passes, b->stream, enqueue4, launch));
+        if (launch) {
+            for (int k = 0; k < n % kTubeSteps; ++k) {
+                HIPTRY(mrt::k_step(b->prec, b->d_insts, b->d_items, b->nitems, b->f[b->cur],
+                                   b->f[1 - b->cur], b->d_health, b->grid, b->nt, false, b->stream));
+                b->cur ^= 1;
+            }
+        }
+        return MRT_OK;
+    }
     if (b->per_pass == 2) {
         // two steps per pass, an odd last step by the single-step kernel;
         // the reflecting-wall ghosts are refilled before every launch
@@ -1362,8 +1415,18 @@ int mrt_batch_set_tile(mrt_batch* b, int rows, int grid) {
 int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows) {
     if (!b) return MRT_EINVAL;
     std::string& ctx_err = b->err;
-    if (steps != 1 && steps != 2) return (b->err = "steps per pass: 1 or 2", MRT_EINVAL);
+    if (steps != 1 && steps != 2 && steps != kTubeSteps)
+        return (b->err = "steps per pass: 1, 2 or 4", MRT_EINVAL);
     if (rows < 0 || rows > MRT_MAX_BAND_ROWS_2) return (b->err = "rows: 0 (default) to 32", MRT_EINVAL);
+    if (steps == kTubeSteps) {
+        if (!tube_march_ok(b))
+            return (b->err = "four steps per pass: FP32 storage and every instance four periodic rows "
+                             "with fixed-equilibrium x sides", MRT_EINVAL);
+        if (!b->d_items4) {
+            const int rc = batch_items4(b);
+            if (rc != MRT_OK) return rc;
+        }
+    }
     if (steps == 2) {
         const int r = rows > 0 ? rows : MRT_MAX_BAND_ROWS_2;
         if (r != b->rows2 || !b->d_items2) {
@@ -1374,6 +1437,7 @@ int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows) {
     b->per_pass = steps;
     b->graphs.clear();
     b->graphs2.clear();
+    b->graphs4.clear();
     // the two-step path leaves the reflecting ghosts of the current state
     // stale; the single-step kernel with in-kernel walls expects them current
     if (b->any_reflect)
@@ -1385,7 +1449,7 @@ int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows) {
 int mrt_batch_get_steps_per_pass(const mrt_batch* b, int* steps, int* rows) {
     if (!b) return MRT_EINVAL;
     if (steps) *steps = b->per_pass;
-    if (rows) *rows = b->per_pass == 2 ? b->rows2 : b->rows;
+    if (rows) *rows = b->per_pass == kTubeSteps ? 4 : (b->per_pass == 2 ? b->rows2 : b->rows);
     return MRT_OK;
 }
 
@@ -1469,6 +1533,25 @@ int mrt_batch_autotune(mrt_batch* b, int steps) {
             HIPTRY(hipMemcpyAsync(b->f[b->cur], save, bytes, hipMemcpyDeviceToDevice, b->stream));
         }
     }
+    // the tube march, per step
+    if (tube_march_ok(b)) {
+        if (batch_items4(b) != MRT_OK) return MRT_EDEVICE;
+        b->per_pass = kTubeSteps;
+        const int steps4 = kTubeSteps * std::max(1, (steps + kTubeSteps - 1) / kTubeSteps);
+        mrt_batch_step(b, steps4);    // capture + warm-up
+        HIPTRY(hipEventRecord(e0, b->stream));
+        mrt_batch_step(b, steps4);
+        HIPTRY(hipEventRecord(e1, b->stream));
+        HIPTRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / float(steps4) < best) {
+            best = ms / float(steps4);
+            best_pass = kTubeSteps;
+        }
+        b->cur = cur0;
+        HIPTRY(hipMemcpyAsync(b->f[b->cur], save, bytes, hipMemcpyDeviceToDevice, b->stream));
+    }
     HIPTRY(hipStreamSynchronize(b->stream));
     HIPTRY(hipEventDestroy(e0));
     HIPTRY(hipEventDestroy(e1));
@@ -1477,6 +1560,7 @@ int mrt_batch_autotune(mrt_batch* b, int steps) {
     b->per_pass = 1;
     int rc = mrt_batch_set_tile(b, best_rows, best_grid);
     if (rc == MRT_OK && best_pass == 2) rc = mrt_batch_set_steps_per_pass(b, 2, best_rows2);
+    if (rc == MRT_OK && best_pass == kTubeSteps) rc = mrt_batch_set_steps_per_pass(b, kTubeSteps, 0);
     HIPTRY(hipStreamSynchronize(b->stream));
     return rc;
 }
@@ -1488,7 +1572,9 @@ void mrt_batch_destroy(mrt_batch* b) {
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     b->graphs.clear();
     b->graphs2.clear();
+    b->graphs4.clear();
     if (b->d_items2) (void)hipFree(b->d_items2);
+    if (b->d_items4) (void)hipFree(b->d_items4);
     if (b->f[0]) (void)hipFree(b->f[0]);
     if (b->f[1]) (void)hipFree(b->f[1]);
     if (b->d_insts) (void)hipFree(b->d_insts);

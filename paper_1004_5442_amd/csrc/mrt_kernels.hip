@@ -1198,6 +1198,166 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_partials(const double* 
     if (t < 16) ds[t] += red[0][t];
 }
 
+// ------------------------------------------------------------- tube march
+
+}  // namespace mrt
+
+#include "mrt_tube.h"
+
+namespace mrt {
+
+// Several time steps per pass for grids of four periodic rows whose x sides
+// hold fixed equilibria (the shock tubes of section (b)).  All four rows of
+// a tube sit in the registers of one block, so the block can advance them
+// L steps before it stores: level k + 1 of row r is the single-step update
+// of rows r - 1, r, r + 1 (mod 4) of level k.  A block covers the 256
+// columns x0 - L .. x0 + 255 - L (lane l = 64 w + lane at x0 - L + l);
+// level k is exact on the lanes k <= l <= 255 - k, since each level needs
+// one more column on either side, so a block stores f^{n+L} of the
+// 256 - 2L columns x0 .. x0 + 255 - 2L and the tube's next block starts
+// there (the overlap is recomputed: 2L of 256 lanes; L = kTubeSteps,
+// kTubeWidth stored columns).  No column outside
+// the block is needed: the halo-column computation of the two-step march
+// disappears.  The ghost columns x = -1 and x = nx keep their side's
+// equilibrium at every level; lanes further out carry values that reach no
+// stored cell.  Per level the edge lanes of the four waves swap the four
+// rows' x-moving populations through LDS (double buffered: one barrier per
+// level).  The state crosses the memory interface once per L steps.
+
+template <typename S>
+struct TubeEdges {
+    S v[2][kWaves][2][4][12];      // [slot][wave][lane 0 / 63][row][x-moving population]
+};
+
+template <typename S, typename C, bool COMP, bool NT, int L>
+__device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
+                                           const S* __restrict__ fin, S* __restrict__ fout,
+                                           unsigned* __restrict__ health, TubeEdges<S>& lds) {
+    static_assert(L % 2 == 0, "levels alternate between two register sets");
+    const int lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int l = 64 * wv + lane;
+    const int nx = P->nx;
+    const int x = x0 - L + l;
+    const long long plane = P->plane;
+    const S* __restrict__ fi = fin + P->off;
+    S* __restrict__ fo = fout + P->off;
+    const unsigned origin = unsigned(P->origin), pitch = unsigned(P->pitch);
+    // load column: lanes outside the grid and its ghost ring read the ghost
+    // column of their side (values that reach no stored cell)
+    const unsigned cx = unsigned(x < -1 ? -1 : (x > nx ? nx : x));
+    const C b = C(P->b), binv = C(P->binv);
+    // whether this wave holds the west (x = -1) or east (x = nx) ghost column
+    const int xw = x0 - L + 64 * wv;
+    const bool wave_west = xw <= -1 && xw + 63 >= -1, wave_east = xw <= nx && xw + 63 >= nx;
+    const bool edge_lane = lane == 0 || lane == 63;
+    const int eside = lane == 0 ? 0 : 1;
+    const int nwave = lane == 0 ? wv - 1 : wv + 1;
+    const int nside = lane == 0 ? 1 : 0;
+    const bool hlds = edge_lane && nwave >= 0 && nwave < kWaves;
+    bool healthy = true;
+
+    S A[4][16], B[4][16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const unsigned o = origin + unsigned(r) * pitch;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            A[r][i] = (fi + (long long)i * plane)[o + cx];
+            B[r][i] = S(0);
+        }
+    }
+    // dst = level k + 1 from src = level k
+    auto level = [&](S (&src)[4][16], S (&dst)[4][16], int k) {
+        // the ghost columns: their side's equilibrium at every level (the
+        // side index is wave-uniform, so the values come from scalar loads)
+        if (k > 0 && wave_west && x == -1) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) src[r][i] = S(P->ghost[XLO][i]);
+        }
+        if (k > 0 && wave_east && x == nx) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) src[r][i] = S(P->ghost[XHI][i]);
+        }
+        if (edge_lane) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) lds.v[k & 1][wv][eside][r][xslot(i)] = src[r][i];
+        }
+        __syncthreads();
+        const bool valid = l > k && l < 255 - k && x >= 0 && x < nx;
+        ConstInst* __restrict__ Pc = reload(P);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            S h[16];
+            no_value(h);
+            if (hlds) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    if (moves_x(i)) h[i] = lds.v[k & 1][nwave][nside][r][xslot(i)];
+            }
+            S cdt[16];
+            C rho, Pp;
+            cell_collision<C, COMP>(src[r], b, binv, Pc->sdt, cdt, rho, Pp);
+            healthy = healthy && (!valid || (rho > C(0) && Pp > C(0)));
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const S W = moves_x(i) ? from_left(src[r][i], h[i]) : S(0);
+                const S E = moves_x(i) ? from_right(src[r][i], h[i]) : S(0);
+                dst[r][i] = site_update(Pc, i, src[r][i], W, E, src[(r + 3) & 3][i],
+                                        src[(r + 1) & 3][i], cdt[i]);
+            }
+            // the row's new values are materialised here, in row order: left
+            // free, the compiler sinks every row's update to the next level
+            // and overlaps the four rows' collisions (412 registers)
+#pragma unroll
+            for (int i = 0; i < 16; ++i) asm volatile("" : "+v"(dst[r][i]));
+        }
+    };
+    for (int k = 0; k < L; k += 2) {
+        level(A, B, k);
+        level(B, A, k + 1);
+    }
+    if (x >= 0 && x < nx && l >= L && l <= 255 - L) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const unsigned o = origin + unsigned(r) * pitch + unsigned(x);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                S* p = fo + (long long)i * plane + o;
+                if constexpr (NT)
+                    __builtin_nontemporal_store(A[r][i], p);
+                else
+                    *p = A[r][i];
+            }
+        }
+    }
+    if (!healthy) atomicOr(health, 1u);
+}
+
+template <typename S, typename C, bool COMP, bool NT, int L>
+__global__ __launch_bounds__(256, 2) void tube_kernel(const Inst* __restrict__ insts,
+                                                      const Item* __restrict__ items, int nitems,
+                                                      const S* __restrict__ fin, S* __restrict__ fout,
+                                                      unsigned* __restrict__ health) {
+    __shared__ TubeEdges<S> lds;
+    ConstInst* cinsts = (ConstInst*)insts;
+    ConstItem* citems = (ConstItem*)items;
+    // XCD-aware item order as in step_kernel
+    const int per = (nitems + 7) >> 3;
+    for (int q = blockIdx.x; q < 8 * per; q += gridDim.x) {
+        const int w = (q & 7) * per + (q >> 3);
+        if (w >= nitems) continue;
+        tube_block<S, C, COMP, NT, L>(cinsts + citems[w].inst, citems[w].x0, fin, fout, health, lds);
+        __syncthreads();   // the next item reuses the LDS buffers
+    }
+}
 
 // ------------------------------------------------- scheme variants
 //
@@ -1462,6 +1622,22 @@ hipError_t launch_step2(const Inst* insts, const Item* items, int nitems, const 
     return hipGetLastError();
 }
 
+template <typename S, typename C, bool COMP>
+hipError_t launch_tube(const Inst* insts, const Item* items, int nitems, const void* fin, void* fout,
+                       unsigned* health, int grid, bool nt, hipStream_t st) {
+    if (nitems <= 0) return hipSuccess;
+    const int blocks = grid > 0 ? grid : 8 * ((nitems + 7) / 8);
+    const S* in = static_cast<const S*>(fin);
+    S* out = static_cast<S*>(fout);
+    if (nt)
+        hipLaunchKernelGGL((tube_kernel<S, C, COMP, true, kTubeSteps>), dim3(blocks), dim3(256), 0, st,
+                           insts, items, nitems, in, out, health);
+    else
+        hipLaunchKernelGGL((tube_kernel<S, C, COMP, false, kTubeSteps>), dim3(blocks), dim3(256), 0, st,
+                           insts, items, nitems, in, out, health);
+    return hipGetLastError();
+}
+
 }  // namespace mrt
 
 // Entry points used by the host library (mrt_api.hip); precision codes as in
@@ -1507,6 +1683,17 @@ hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, c
         case 0: return launch_step2<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
         case 1: return launch_step2<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
         case 2: return launch_step2<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, wrap4, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// kTubeSteps steps of four-row periodic tubes with fixed-equilibrium x
+// sides, FP32 storage only (prec 1 or 2), from fin to fout.
+hipError_t k_tube(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
+                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+    switch (prec) {
+        case 1: return launch_tube<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        case 2: return launch_tube<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
         default: return hipErrorInvalidValue;
     }
 }

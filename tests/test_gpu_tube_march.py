@@ -1,0 +1,159 @@
+"""GPU parity of the tube march: four time steps per pass for batches of
+four-row periodic tubes with fixed-equilibrium x sides (the shock tubes of
+section (b)), each block holding all four rows of a tube in registers and
+storing 248 of the 256 columns it computes.  Against the FP64 oracle and
+against the same batch advanced one step per pass."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from helpers import field_errors, fp32_tolerances, one_row, oracle_run
+from oracle import mrt
+from paper_1004_5442_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs the GPU", allow_module_level=True)
+
+from paper_1004_5442_amd.batch import Batch  # noqa: E402
+from paper_1004_5442_amd.lib import MRTError, UnstableError  # noqa: E402
+
+TUBE_WIDTH = 248      # columns one block stores (256 less one per step on either side)
+
+
+def _tubes(sizes, seed=0):
+    """Shock tubes of the given lengths: one block and its edges (1, 3,
+    247, 248, 249), two and three blocks with ragged ends."""
+    out = []
+    for k, nx in enumerate(sizes):
+        c = W.tube_batch(1, seed=seed + k, nx_range=(nx, nx))[0]
+        out.append(dataclasses.replace(c, name=f"tube_nx{nx}"))
+    return out
+
+
+SIZES = [1, 3, 200, TUBE_WIDTH - 1, TUBE_WIDTH, TUBE_WIDTH + 1, 2 * TUBE_WIDTH,
+         2 * TUBE_WIDTH + 1, 745]
+
+
+@pytest.mark.parametrize("precision", ["fp32_eq64", "fp32"])
+def test_tube_march_matches_oracle_and_single_steps(precision):
+    """13 steps per call over three calls (three four-step passes and one
+    single step each) on tubes of one to three blocks: every tube against
+    the FP64 oracle (the stated 1e-5 per field, or twice the FP32-storage
+    error) and against the same batch one step per pass.  The pure FP32
+    form equals it bit for bit (the same per-cell arithmetic, its FP32
+    transforms fused the same way everywhere); with the FP64 collision the
+    compiler may fuse the FP64 arithmetic differently in the two kernels, so
+    the bound is two FP32 ulps of the population scale."""
+    cases = _tubes(SIZES)
+    one = Batch(cases, precision)
+    tube = Batch(cases, precision)
+    tube.set_steps_per_pass(4)
+    assert tube.steps_per_pass() == (4, 4)
+    for call in range(3):
+        print(f"call {call} {precision}", flush=True)
+        one.step(13)
+        tube.step(13)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 39)
+        err = field_errors(tube.moments(i), mrt.macroscopic(want, p.b))
+        tol = fp32_tolerances(c, 39, want)
+        a, b = tube.populations(i), one.populations(i)
+        d = float(np.max(np.abs(a - b)) / np.abs(b).max())
+        print(c.name, err, "vs one step per pass", d, flush=True)
+        assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+        if precision == "fp32":
+            assert d == 0.0, (c.name, d)
+        else:
+            assert d <= 2.4e-7, (c.name, d)
+
+
+def test_tube_march_across_graph_replays_and_step_counts():
+    """Step counts that exercise the captured passes (64 passes per graph
+    replay) and every remainder of single steps (1 to 3), against one step
+    per pass."""
+    cases = _tubes([300, 600], seed=5)
+    one = Batch(cases, "fp32")
+    tube = Batch(cases, "fp32")
+    tube.set_steps_per_pass(4)
+    for n in (1, 2, 3, 4, 7, 258):
+        print(f"{n} steps", flush=True)
+        one.step(n)
+        tube.step(n)
+        for i in range(len(cases)):
+            assert np.array_equal(tube.populations(i), one.populations(i)), (n, i)
+
+
+def test_tube_march_rejected_outside_its_cover():
+    """FP64 storage, an instance that is not a four-row periodic tube, or
+    non-equilibrium x sides: four steps per pass are refused."""
+    tubes = _tubes([300])
+    with pytest.raises(MRTError):
+        Batch(tubes, "fp64").set_steps_per_pass(4)
+    eight = dataclasses.replace(W.tube_batch(1, seed=1, nx_range=(300, 300), ny=8)[0])
+    with pytest.raises(MRTError):
+        Batch(tubes + [eight], "fp32_eq64").set_steps_per_pass(4)
+    outflow = dataclasses.replace(tubes[0], bc=("eq", "outflow", "periodic", "periodic"))
+    with pytest.raises(MRTError):
+        Batch([outflow], "fp32_eq64").set_steps_per_pass(4)
+    with pytest.raises(MRTError):
+        Batch(tubes, "fp32_eq64").set_steps_per_pass(3)
+
+
+def test_tube_march_reports_unhealthy_cells():
+    """A tube stepped far past its stability limit (dt 10^5 times larger,
+    rates scaled to keep s dt) goes negative at its diaphragm within the
+    first four-step pass: the health flag reports it, and the flag is
+    cleared by the report."""
+    cases = _tubes([300, 300], seed=2)
+    c = cases[1]
+    bad = dataclasses.replace(c, dt=0.5, s=list(np.asarray(c.s) * (c.dt / 0.5)))
+    b = Batch([cases[0], bad], "fp32_eq64")
+    b.set_steps_per_pass(4)
+    b.step(4)
+    with pytest.raises(UnstableError):
+        b.moments(0)
+    good = Batch(cases, "fp32_eq64")
+    good.set_steps_per_pass(4)
+    good.step(8)
+    good.moments(0)
+
+
+_FULL = {}
+
+
+def _full_tube_march():
+    if not _FULL:
+        cases = W.tube_batch(512, seed=0)
+        b = Batch(cases, "fp32_eq64")
+        b.set_steps_per_pass(4)
+        b.step(1000)
+        r = [c.meta["pressure_ratio"] for c in cases]
+        g = [c.gamma for c in cases]
+        sel = {"max_pressure_ratio": int(np.argmax(r)), "min_gamma": int(np.argmin(g)),
+               "max_gamma": int(np.argmax(g)), "longest": int(np.argmax([c.nx for c in cases]))}
+        _FULL["cases"] = cases
+        _FULL["sel"] = sel
+        _FULL["moments"] = {i: b.moments(i) for i in set(sel.values())}
+        b.close()
+    return _FULL
+
+
+@pytest.mark.parametrize("which", ["max_pressure_ratio", "min_gamma", "max_gamma", "longest"])
+def test_full_batch_512_tubes_tube_march(which):
+    """The 512-tube batch, 1000 steps by the tube march, FP32 storage with
+    FP64 collision: the selected tube's rho, u, T against the FP64 oracle
+    (run on one row), to the stated 1e-5 or twice the FP32-storage error."""
+    full = _full_tube_march()
+    i = full["sel"][which]
+    c = full["cases"][i]
+    c1 = one_row(c)
+    want, p = oracle_run(c1, 1000)
+    got = [a[:1] for a in full["moments"][i]]
+    err = field_errors(got, mrt.macroscopic(want, p.b))
+    tol = fp32_tolerances(c1, 1000, want)
+    print(which, c.name, f"nx {c.nx}", "err", err, "tol", tol, flush=True)
+    assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
