@@ -500,8 +500,10 @@ def extra_legs(head, prec, steps):
         c = W.strong_shock_tube(1.4, False)
         rr = time_solver(c, "fp64", 16 * k, 64)
         return {"mlups": round(rr["mlups"], 1), "ms_per_step": round(rr["ms_per_step"], 5),
+                "steps_per_pass": rr["per_pass"],
                 "steps_for_t_0.13_s": round(c.nsteps * rr["ms_per_step"] / 1e3, 3),
-                "note": "1,100 cells: launch-latency bound (captured graphs of 64 steps)"}
+                "note": "1,100 cells: launch-latency bound (captured graphs of 64 passes; the "
+                        "autotuner's steps per pass, 4 = the tube march)"}
 
     return {
         "fp32_eq64_one_step_per_pass": one_step,

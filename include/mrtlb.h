@@ -192,8 +192,17 @@ int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
  * two edge columns, which halves the memory traffic per step.  An odd last
  * step of mrt_step runs the single-step kernel.  Every precision; the
  * default scheme only (variants set by mrt_set_scheme run one step per
- * pass).  Synchronises.
- * Errors: MRT_EINVAL (steps not 1 or 2, rows out of range). */
+ * pass).
+ * steps = 4, the tube march: for grids of 1, 2 or 4 rows, periodic in y,
+ * with fixed-equilibrium x sides (the shock tubes of section (b)): one
+ * launch advances four steps of Eq. 3, each block holding all rows of 256
+ * columns in registers and storing the 248 that are exact after four steps
+ * (the overlap is recomputed); rows is ignored; steps beyond a multiple of
+ * four run one by one.  Results equal single steps to rounding order
+ * (measured bit-identical in the FP32 storage forms).  mrt_autotune times it
+ * too on such grids.  Synchronises.
+ * Errors: MRT_EINVAL (steps not 1, 2 or 4; rows out of range; 4 on another
+ * grid). */
 #define MRT_MAX_BAND_ROWS_2 32
 int mrt_set_steps_per_pass(mrt_ctx* ctx, int steps, int rows);
 int mrt_get_steps_per_pass(const mrt_ctx* ctx, int* steps, int* rows);
@@ -352,13 +361,9 @@ int mrt_batch_set_tile(mrt_batch* b, int rows_per_item, int grid_blocks);
 int mrt_batch_get_tile(const mrt_batch* b, int* rows_per_item, int* grid_blocks);
 /* As mrt_set_steps_per_pass, for every instance of the batch (default 1;
  * rows 0 = 32, bands never exceed an instance's height).  steps = 4: the
- * tube march, for batches whose every instance has four periodic rows and
- * fixed-equilibrium x sides (the shock tubes of section (b)) in FP32
- * storage: one pass advances a tube four steps (Eq. 3 each), each block
- * holding all four rows in registers and storing 248 of the 256 columns it
- * computes; rows is ignored; a step count that is not a multiple of four
- * ends with single steps.  Results equal four single steps to rounding
- * order (bit for bit in MRT_FP32).  Synchronises.
+ * tube march, for batches whose instances all have the same height of 1, 2
+ * or 4 periodic rows and fixed-equilibrium x sides (the shock tubes of
+ * section (b)), any precision.  Synchronises.
  * Errors: MRT_EINVAL (steps not 1, 2 or 4; rows out of range; 4 on a batch
  * the tube march does not cover). */
 int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows);

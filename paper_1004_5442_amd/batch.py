@@ -74,8 +74,8 @@ class Batch:
 
     def set_steps_per_pass(self, steps: int, rows: int = 0):
         """1, 2 or 4 time steps per kernel pass (mrt_batch_set_steps_per_pass;
-        4: the tube march, for four-row periodic tubes with fixed-equilibrium
-        x sides in FP32 storage)."""
+        4: the tube march, for batches of tubes of one common height of 1, 2
+        or 4 periodic rows with fixed-equilibrium x sides)."""
         self._check(L.raw().mrt_batch_set_steps_per_pass(self._h, int(steps), int(rows)))
 
     def steps_per_pass(self):

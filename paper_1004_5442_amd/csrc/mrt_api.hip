@@ -28,7 +28,7 @@ hipError_t k_step(int prec, const Inst* insts, const Item* items, int nitems, co
 hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
                    void* fout, unsigned* health, int grid, bool nt, bool wrap4, hipStream_t st);
 hipError_t k_tube(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st);
+                  void* fout, unsigned* health, int grid, bool nt, int ny, hipStream_t st);
 hipError_t k_variant(int prec, const Inst* P, int nx, int ny, int scheme, bool reflect,
                      const void* fin, void* fout, void* tmp, unsigned* health, hipStream_t st);
 hipError_t k_adjoint(int prec, const Inst* insts, const Item* items, int nitems, const void* lin,
@@ -349,6 +349,9 @@ struct mrt_ctx {
     int nitems2 = 0, rows2 = 0;
     bool wrap4 = false;              // a two-step band is a whole periodic height of 4 rows
     GraphCache graphs2;              // captured two-step passes
+    Item* d_items4 = nullptr;        // work items of the tube march
+    int nitems4 = 0;
+    GraphCache graphs4;              // captured tube-march passes
     bool eager = false;              // launch step by step (the tile autotuner)
     int scheme = 0;                  // MRT_SCHEME_* flags
     void* f_tmp = nullptr;           // post-collision state of the split scheme
@@ -421,6 +424,31 @@ int build_items2(mrt_ctx* c, int rows) {
     c->rows2 = rows;
     c->wrap4 = wraps_four_rows(c->inst, rows);
     c->graphs2.clear();
+    return MRT_OK;
+}
+
+// Whether the tube march (kTubeSteps steps per pass, mrt_kernels.hip) can
+// advance an instance: 1, 2 or 4 periodic rows, fixed-equilibrium x sides.
+bool tube_inst_ok(const Inst& I) {
+    return (I.ny == 1 || I.ny == 2 || I.ny == 4) && I.bc[2] == MRT_BC_PERIODIC &&
+           I.bc[3] == MRT_BC_PERIODIC && I.bc[0] == MRT_BC_EQ && I.bc[1] == MRT_BC_EQ;
+}
+
+// Tube-march work items of an instance: kTubeWidth-column chunks.
+void add_tube_items(std::vector<Item>& items, int inst, int nx, int ny) {
+    for (int x0 = 0; x0 < nx; x0 += kTubeWidth) items.push_back(Item{inst, x0, 0, ny});
+}
+
+int build_items4(mrt_ctx* c) {
+    std::string& ctx_err = c->err;
+    std::vector<Item> items;
+    add_tube_items(items, 0, c->nx, c->ny);
+    if (c->d_items4) HIPTRY(hipFree(c->d_items4));
+    c->d_items4 = nullptr;
+    HIPTRY(hipMalloc(&c->d_items4, items.size() * sizeof(Item)));
+    HIPTRY(hipMemcpy(c->d_items4, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+    c->nitems4 = int(items.size());
+    c->graphs4.clear();
     return MRT_OK;
 }
 
@@ -616,6 +644,30 @@ static int step_impl(mrt_ctx* c, int n, bool launch) {
     // step.  The per-cell nine-point kernel writes none, so its ghosts
     // (corners too) are always refilled (the split scheme refills those of
     // its post-collision state itself)
+    if (c->per_pass == kTubeSteps && c->scheme == 0) {
+        // the tube march (no reflecting sides), the remaining steps one by one
+        auto enqueue4 = [&](int cur, hipStream_t st) -> hipError_t {
+            return mrt::k_tube(c->prec, c->d_inst, c->d_items4, c->nitems4, c->f[cur], c->f[1 - cur],
+                               c->d_health, 0, c->nt, c->ny, st);
+        };
+        const int passes = n / kTubeSteps;
+        if (c->eager || passes == 1) {
+            if (launch)
+                for (int k = 0; k < passes; ++k) {
+                    HIPTRY(enqueue4(c->cur, c->stream));
+                    c->cur ^= 1;
+                }
+        } else if (passes > 1) {
+            HIPTRY(run_graphs(c->graphs4, c->cur, passes, c->stream, enqueue4, launch));
+        }
+        if (launch)
+            for (int k = 0; k < n % kTubeSteps; ++k) {
+                HIPTRY(mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, c->f[c->cur], c->f[1 - c->cur],
+                                   c->d_health, c->grid, c->nt, c->walls, c->stream));
+                c->cur ^= 1;
+            }
+        return MRT_OK;
+    }
     if (c->per_pass == 2 && c->scheme == 0) {
         // two steps per pass; an odd last step by the single-step kernel.
         // Neither writes the reflecting-wall ghosts of its output here: the
@@ -773,8 +825,18 @@ int mrt_set_tile(mrt_ctx* c, int rows, int grid) {
 int mrt_set_steps_per_pass(mrt_ctx* c, int steps, int rows) {
     if (!c) return MRT_EINVAL;
     std::string& ctx_err = c->err;
-    if (steps != 1 && steps != 2) return ctx_fail(c, MRT_EINVAL, "steps per pass: 1 or 2");
+    if (steps != 1 && steps != 2 && steps != kTubeSteps)
+        return ctx_fail(c, MRT_EINVAL, "steps per pass: 1, 2 or 4");
     if (rows < 0 || rows > MRT_MAX_BAND_ROWS_2) return ctx_fail(c, MRT_EINVAL, "rows: 0 (default) to 32");
+    if (steps == kTubeSteps) {
+        if (!tube_inst_ok(c->inst))
+            return ctx_fail(c, MRT_EINVAL, "four steps per pass: 1, 2 or 4 periodic rows and "
+                                           "fixed-equilibrium x sides");
+        if (!c->d_items4) {
+            const int rc = build_items4(c);
+            if (rc != MRT_OK) return rc;
+        }
+    }
     if (steps == 2) {
         const int r = std::min(rows > 0 ? rows : default_rows2(c->nx, c->ny), c->ny);
         if (r != c->rows2 || !c->d_items2) {
@@ -785,6 +847,7 @@ int mrt_set_steps_per_pass(mrt_ctx* c, int steps, int rows) {
     c->per_pass = steps;
     c->graphs.clear();
     c->graphs2.clear();
+    c->graphs4.clear();
     // the two-step path leaves the reflecting ghosts of the current state
     // stale; the single-step kernel expects them current
     if (c->params_set && c->fields_set) {
@@ -820,7 +883,7 @@ int mrt_set_scheme(mrt_ctx* c, int flags) {
 int mrt_get_steps_per_pass(const mrt_ctx* c, int* steps, int* rows) {
     if (!c) return MRT_EINVAL;
     if (steps) *steps = c->per_pass;
-    if (rows) *rows = c->per_pass == 2 ? c->rows2 : c->rows;
+    if (rows) *rows = c->per_pass == kTubeSteps ? c->ny : (c->per_pass == 2 ? c->rows2 : c->rows);
     return MRT_OK;
 }
 
@@ -909,6 +972,26 @@ int mrt_autotune(mrt_ctx* c, int steps) {
             HIPTRY(hipMemcpyAsync(c->f[c->cur], save, bytes, hipMemcpyDeviceToDevice, c->stream));
         }
     }
+    // the tube march, per step
+    if (tube_inst_ok(c->inst) && c->scheme == 0) {
+        if (build_items4(c) != MRT_OK) return MRT_EDEVICE;
+        c->per_pass = kTubeSteps;
+        const int steps4 = kTubeSteps * std::max(1, (steps + kTubeSteps - 1) / kTubeSteps);
+        c->eager = true;
+        mrt_step(c, kTubeSteps);
+        HIPTRY(hipEventRecord(e0, c->stream));
+        mrt_step(c, steps4);
+        HIPTRY(hipEventRecord(e1, c->stream));
+        c->eager = false;
+        HIPTRY(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPTRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms / float(steps4) < best) {
+            best = ms / float(steps4);
+            best_pass = kTubeSteps;
+        }
+        HIPTRY(hipMemcpyAsync(c->f[c->cur], save, bytes, hipMemcpyDeviceToDevice, c->stream));
+    }
     HIPTRY(hipStreamSynchronize(c->stream));
     HIPTRY(hipEventDestroy(e0));
     HIPTRY(hipEventDestroy(e1));
@@ -920,6 +1003,7 @@ int mrt_autotune(mrt_ctx* c, int steps) {
     if (best_pass == 2 && build_items2(c, best_rows2) != MRT_OK) return MRT_EDEVICE;
     c->graphs.clear();
     c->graphs2.clear();
+    c->graphs4.clear();
     HIPTRY(hipStreamSynchronize(c->stream));
     return MRT_OK;
 }
@@ -935,9 +1019,11 @@ void mrt_destroy(mrt_ctx* c) {
     if (c->d_items) (void)hipFree(c->d_items);
     if (c->d_items_adj) (void)hipFree(c->d_items_adj);
     if (c->d_items2) (void)hipFree(c->d_items2);
+    if (c->d_items4) (void)hipFree(c->d_items4);
     if (c->f_tmp) (void)hipFree(c->f_tmp);
     c->graphs.clear();
     c->graphs2.clear();
+    c->graphs4.clear();
     if (c->d_stage) (void)hipFree(c->d_stage);
     if (c->d_partial) (void)hipFree(c->d_partial);
     if (c->d_health) (void)hipFree(c->d_health);
@@ -1135,7 +1221,7 @@ struct mrt_batch {
     bool wrap4 = false;                     // some band is a whole periodic height of 4 rows
     GraphCache graphs2;                     // captured two-step passes
     Item* d_items4 = nullptr;               // work items of the tube march
-    int nitems4 = 0;
+    int nitems4 = 0, tube_ny = 0;           // tube_ny: the rows of every instance
     GraphCache graphs4;                     // captured tube-march passes
     std::string err;
 };
@@ -1179,14 +1265,11 @@ int batch_items2(mrt_batch* b, int rows) {
 }
 
 // Whether the tube march (kTubeSteps steps per pass) can advance the
-// batch: FP32 storage, and every instance four periodic rows with
+// batch: every instance the same height of 1, 2 or 4 periodic rows with
 // fixed-equilibrium x sides.
 bool tube_march_ok(const mrt_batch* b) {
-    if (b->prec == MRT_FP64) return false;
     for (const Inst& I : b->insts)
-        if (I.ny != 4 || I.bc[2] != MRT_BC_PERIODIC || I.bc[3] != MRT_BC_PERIODIC ||
-            I.bc[0] != MRT_BC_EQ || I.bc[1] != MRT_BC_EQ)
-            return false;
+        if (!tube_inst_ok(I) || I.ny != b->insts[0].ny) return false;
     return true;
 }
 
@@ -1194,8 +1277,8 @@ bool tube_march_ok(const mrt_batch* b) {
 int batch_items4(mrt_batch* b) {
     std::string& ctx_err = b->err;
     std::vector<Item> items;
-    for (int i = 0; i < b->count; ++i)
-        for (int x0 = 0; x0 < b->insts[i].nx; x0 += kTubeWidth) items.push_back(Item{i, x0, 0, 4});
+    for (int i = 0; i < b->count; ++i) add_tube_items(items, i, b->insts[i].nx, b->insts[i].ny);
+    b->tube_ny = b->insts[0].ny;
     if (b->d_items4) HIPTRY(hipFree(b->d_items4));
     b->d_items4 = nullptr;
     HIPTRY(hipMalloc(&b->d_items4, items.size() * sizeof(Item)));
@@ -1316,7 +1399,7 @@ static int batch_step_impl(mrt_batch* b, int n, bool launch) {
         // equilibria, its y sides periodic), the remaining steps one by one
         auto enqueue4 = [&](int cur, hipStream_t st) -> hipError_t {
             return mrt::k_tube(b->prec, b->d_insts, b->d_items4, b->nitems4, b->f[cur], b->f[1 - cur],
-                               b->d_health, 0, b->nt, st);
+                               b->d_health, 0, b->nt, b->tube_ny, st);
         };
         const int passes = n / kTubeSteps;
         if (passes > 0) HIPTRY(run_graphs(b->graphs4, b->cur, passes, b->stream, enqueue4, launch));
@@ -1420,8 +1503,8 @@ int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows) {
     if (rows < 0 || rows > MRT_MAX_BAND_ROWS_2) return (b->err = "rows: 0 (default) to 32", MRT_EINVAL);
     if (steps == kTubeSteps) {
         if (!tube_march_ok(b))
-            return (b->err = "four steps per pass: FP32 storage and every instance four periodic rows "
-                             "with fixed-equilibrium x sides", MRT_EINVAL);
+            return (b->err = "four steps per pass: every instance 1, 2 or 4 periodic rows (the same "
+                             "for all) with fixed-equilibrium x sides", MRT_EINVAL);
         if (!b->d_items4) {
             const int rc = batch_items4(b);
             if (rc != MRT_OK) return rc;
@@ -1449,7 +1532,7 @@ int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows) {
 int mrt_batch_get_steps_per_pass(const mrt_batch* b, int* steps, int* rows) {
     if (!b) return MRT_EINVAL;
     if (steps) *steps = b->per_pass;
-    if (rows) *rows = b->per_pass == kTubeSteps ? 4 : (b->per_pass == 2 ? b->rows2 : b->rows);
+    if (rows) *rows = b->per_pass == kTubeSteps ? b->tube_ny : (b->per_pass == 2 ? b->rows2 : b->rows);
     return MRT_OK;
 }
 

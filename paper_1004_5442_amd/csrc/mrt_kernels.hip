@@ -1206,34 +1206,35 @@ __global__ __launch_bounds__(kReduceThreads) void reduce_partials(const double* 
 
 namespace mrt {
 
-// Several time steps per pass for grids of four periodic rows whose x sides
-// hold fixed equilibria (the shock tubes of section (b)).  All four rows of
-// a tube sit in the registers of one block, so the block can advance them
-// L steps before it stores: level k + 1 of row r is the single-step update
-// of rows r - 1, r, r + 1 (mod 4) of level k.  A block covers the 256
-// columns x0 - L .. x0 + 255 - L (lane l = 64 w + lane at x0 - L + l);
-// level k is exact on the lanes k <= l <= 255 - k, since each level needs
-// one more column on either side, so a block stores f^{n+L} of the
-// 256 - 2L columns x0 .. x0 + 255 - 2L and the tube's next block starts
+// Several time steps per pass for grids of NY = 1, 2 or 4 periodic rows
+// whose x sides hold fixed equilibria (the shock tubes of section (b)).  All
+// rows of a tube sit in the registers of one block, so the block can
+// advance them L steps before it stores: level k + 1 of row r is the
+// single-step update of rows r - 1, r, r + 1 (mod NY) of level k.  A block
+// covers the 256 columns x0 - L .. x0 + 255 - L (lane l = 64 w + lane at
+// x0 - L + l); level k is exact on the lanes k <= l <= 255 - k, since each
+// level needs one more column on either side, so a block stores f^{n+L} of
+// the 256 - 2L columns x0 .. x0 + 255 - 2L and the tube's next block starts
 // there (the overlap is recomputed: 2L of 256 lanes; L = kTubeSteps,
-// kTubeWidth stored columns).  No column outside
-// the block is needed: the halo-column computation of the two-step march
-// disappears.  The ghost columns x = -1 and x = nx keep their side's
-// equilibrium at every level; lanes further out carry values that reach no
-// stored cell.  Per level the edge lanes of the four waves swap the four
-// rows' x-moving populations through LDS (double buffered: one barrier per
-// level).  The state crosses the memory interface once per L steps.
+// kTubeWidth stored columns).  No column outside the block is needed: the
+// halo-column computation of the two-step march disappears.  The ghost
+// columns x = -1 and x = nx keep their side's equilibrium at every level;
+// lanes further out carry values that reach no stored cell.  Per level the
+// edge lanes of the four waves swap the rows' x-moving populations through
+// LDS (double buffered: one barrier per level).  The state crosses the
+// memory interface once per L steps.
 
 template <typename S>
 struct TubeEdges {
     S v[2][kWaves][2][4][12];      // [slot][wave][lane 0 / 63][row][x-moving population]
 };
 
-template <typename S, typename C, bool COMP, bool NT, int L>
+template <typename S, typename C, bool COMP, bool NT, int L, int NY>
 __device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
                                            const S* __restrict__ fin, S* __restrict__ fout,
                                            unsigned* __restrict__ health, TubeEdges<S>& lds) {
     static_assert(L % 2 == 0, "levels alternate between two register sets");
+    static_assert(NY == 1 || NY == 2 || NY == 4, "one, two or four rows");
     const int lane = lane_id();
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int l = 64 * wv + lane;
@@ -1257,9 +1258,9 @@ __device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
     const bool hlds = edge_lane && nwave >= 0 && nwave < kWaves;
     bool healthy = true;
 
-    S A[4][16], B[4][16];
+    S A[NY][16], B[NY][16];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < NY; ++r) {
         const unsigned o = origin + unsigned(r) * pitch;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
@@ -1268,24 +1269,24 @@ __device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
         }
     }
     // dst = level k + 1 from src = level k
-    auto level = [&](S (&src)[4][16], S (&dst)[4][16], int k) {
+    auto level = [&](S (&src)[NY][16], S (&dst)[NY][16], int k) {
         // the ghost columns: their side's equilibrium at every level (the
         // side index is wave-uniform, so the values come from scalar loads)
         if (k > 0 && wave_west && x == -1) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < NY; ++r)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) src[r][i] = S(P->ghost[XLO][i]);
         }
         if (k > 0 && wave_east && x == nx) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < NY; ++r)
 #pragma unroll
                 for (int i = 0; i < 16; ++i) src[r][i] = S(P->ghost[XHI][i]);
         }
         if (edge_lane) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
+            for (int r = 0; r < NY; ++r)
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
                     if (moves_x(i)) lds.v[k & 1][wv][eside][r][xslot(i)] = src[r][i];
@@ -1294,7 +1295,7 @@ __device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
         const bool valid = l > k && l < 255 - k && x >= 0 && x < nx;
         ConstInst* __restrict__ Pc = reload(P);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NY; ++r) {
             S h[16];
             no_value(h);
             if (hlds) {
@@ -1310,8 +1311,8 @@ __device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
             for (int i = 0; i < 16; ++i) {
                 const S W = moves_x(i) ? from_left(src[r][i], h[i]) : S(0);
                 const S E = moves_x(i) ? from_right(src[r][i], h[i]) : S(0);
-                dst[r][i] = site_update(Pc, i, src[r][i], W, E, src[(r + 3) & 3][i],
-                                        src[(r + 1) & 3][i], cdt[i]);
+                dst[r][i] = site_update(Pc, i, src[r][i], W, E, src[(r + NY - 1) % NY][i],
+                                        src[(r + 1) % NY][i], cdt[i]);
             }
             // the row's new values are materialised here, in row order: left
             // free, the compiler sinks every row's update to the next level
@@ -1326,7 +1327,7 @@ __device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
     }
     if (x >= 0 && x < nx && l >= L && l <= 255 - L) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < NY; ++r) {
             const unsigned o = origin + unsigned(r) * pitch + unsigned(x);
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
@@ -1341,11 +1342,15 @@ __device__ __forceinline__ void tube_block(ConstInst* __restrict__ P, int x0,
     if (!healthy) atomicOr(health, 1u);
 }
 
-template <typename S, typename C, bool COMP, bool NT, int L>
-__global__ __launch_bounds__(256, 2) void tube_kernel(const Inst* __restrict__ insts,
-                                                      const Item* __restrict__ items, int nitems,
-                                                      const S* __restrict__ fin, S* __restrict__ fout,
-                                                      unsigned* __restrict__ health) {
+// Two blocks (two waves per SIMD) per CU; FP64 storage with four rows holds
+// two register sets of 64 doubles per lane: one.
+template <typename S, int NY>
+constexpr int tube_waves() { return sizeof(S) == 8 && NY == 4 ? 1 : 2; }
+
+template <typename S, typename C, bool COMP, bool NT, int L, int NY>
+__global__ __launch_bounds__(256, (tube_waves<S, NY>())) void tube_kernel(
+        const Inst* __restrict__ insts, const Item* __restrict__ items, int nitems,
+        const S* __restrict__ fin, S* __restrict__ fout, unsigned* __restrict__ health) {
     __shared__ TubeEdges<S> lds;
     ConstInst* cinsts = (ConstInst*)insts;
     ConstItem* citems = (ConstItem*)items;
@@ -1354,7 +1359,7 @@ __global__ __launch_bounds__(256, 2) void tube_kernel(const Inst* __restrict__ i
     for (int q = blockIdx.x; q < 8 * per; q += gridDim.x) {
         const int w = (q & 7) * per + (q >> 3);
         if (w >= nitems) continue;
-        tube_block<S, C, COMP, NT, L>(cinsts + citems[w].inst, citems[w].x0, fin, fout, health, lds);
+        tube_block<S, C, COMP, NT, L, NY>(cinsts + citems[w].inst, citems[w].x0, fin, fout, health, lds);
         __syncthreads();   // the next item reuses the LDS buffers
     }
 }
@@ -1622,19 +1627,37 @@ hipError_t launch_step2(const Inst* insts, const Item* items, int nitems, const 
     return hipGetLastError();
 }
 
+template <typename S, typename C, bool COMP, bool NT>
+void launch_tube_nt(const Inst* insts, const Item* items, int nitems, const S* fin, S* fout,
+                    unsigned* health, int blocks, int ny, hipStream_t st) {
+    switch (ny) {
+        case 1:
+            hipLaunchKernelGGL((tube_kernel<S, C, COMP, NT, kTubeSteps, 1>), dim3(blocks), dim3(256), 0,
+                               st, insts, items, nitems, fin, fout, health);
+            break;
+        case 2:
+            hipLaunchKernelGGL((tube_kernel<S, C, COMP, NT, kTubeSteps, 2>), dim3(blocks), dim3(256), 0,
+                               st, insts, items, nitems, fin, fout, health);
+            break;
+        default:
+            hipLaunchKernelGGL((tube_kernel<S, C, COMP, NT, kTubeSteps, 4>), dim3(blocks), dim3(256), 0,
+                               st, insts, items, nitems, fin, fout, health);
+            break;
+    }
+}
+
 template <typename S, typename C, bool COMP>
 hipError_t launch_tube(const Inst* insts, const Item* items, int nitems, const void* fin, void* fout,
-                       unsigned* health, int grid, bool nt, hipStream_t st) {
+                       unsigned* health, int grid, bool nt, int ny, hipStream_t st) {
     if (nitems <= 0) return hipSuccess;
+    if (ny != 1 && ny != 2 && ny != 4) return hipErrorInvalidValue;
     const int blocks = grid > 0 ? grid : 8 * ((nitems + 7) / 8);
     const S* in = static_cast<const S*>(fin);
     S* out = static_cast<S*>(fout);
     if (nt)
-        hipLaunchKernelGGL((tube_kernel<S, C, COMP, true, kTubeSteps>), dim3(blocks), dim3(256), 0, st,
-                           insts, items, nitems, in, out, health);
+        launch_tube_nt<S, C, COMP, true>(insts, items, nitems, in, out, health, blocks, ny, st);
     else
-        hipLaunchKernelGGL((tube_kernel<S, C, COMP, false, kTubeSteps>), dim3(blocks), dim3(256), 0, st,
-                           insts, items, nitems, in, out, health);
+        launch_tube_nt<S, C, COMP, false>(insts, items, nitems, in, out, health, blocks, ny, st);
     return hipGetLastError();
 }
 
@@ -1687,13 +1710,14 @@ hipError_t k_step2(int prec, const Inst* insts, const Item* items, int nitems, c
     }
 }
 
-// kTubeSteps steps of four-row periodic tubes with fixed-equilibrium x
-// sides, FP32 storage only (prec 1 or 2), from fin to fout.
+// kTubeSteps steps of tubes of ny = 1, 2 or 4 periodic rows (every
+// instance of the launch) with fixed-equilibrium x sides, from fin to fout.
 hipError_t k_tube(int prec, const Inst* insts, const Item* items, int nitems, const void* fin,
-                  void* fout, unsigned* health, int grid, bool nt, hipStream_t st) {
+                  void* fout, unsigned* health, int grid, bool nt, int ny, hipStream_t st) {
     switch (prec) {
-        case 1: return launch_tube<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, st);
-        case 2: return launch_tube<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, st);
+        case 0: return launch_tube<double, double, false>(insts, items, nitems, fin, fout, health, grid, nt, ny, st);
+        case 1: return launch_tube<float, float, true>(insts, items, nitems, fin, fout, health, grid, nt, ny, st);
+        case 2: return launch_tube<float, double, false>(insts, items, nitems, fin, fout, health, grid, nt, ny, st);
         default: return hipErrorInvalidValue;
     }
 }

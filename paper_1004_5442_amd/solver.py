@@ -147,8 +147,10 @@ class Solver:
         self._check(L.raw().mrt_set_scheme(self._h, flags))
 
     def set_steps_per_pass(self, steps: int, rows: int = 0):
-        """1 or 2 time steps per kernel pass (mrt_set_steps_per_pass); rows:
-        band height of the two-step kernel (0: default)."""
+        """1, 2 or 4 time steps per kernel pass (mrt_set_steps_per_pass);
+        rows: band height of the two-step kernel (0: default).  4: the tube
+        march, for grids of 1, 2 or 4 periodic rows with fixed-equilibrium x
+        sides."""
         self._check(L.raw().mrt_set_steps_per_pass(self._h, int(steps), int(rows)))
 
     def steps_per_pass(self):

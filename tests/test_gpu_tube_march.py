@@ -1,14 +1,14 @@
-"""GPU parity of the tube march: four time steps per pass for batches of
-four-row periodic tubes with fixed-equilibrium x sides (the shock tubes of
-section (b)), each block holding all four rows of a tube in registers and
-storing 248 of the 256 columns it computes.  Against the FP64 oracle and
-against the same batch advanced one step per pass."""
+"""GPU parity of the tube march: four time steps per pass for tubes of 1, 2
+or 4 periodic rows with fixed-equilibrium x sides (the shock tubes of
+section (b)), batched or single, each block holding all rows of a tube in
+registers and storing 248 of the 256 columns it computes.  Against the FP64
+oracle and against the same grids advanced one step per pass."""
 import dataclasses
 
 import numpy as np
 import pytest
 
-from helpers import field_errors, fp32_tolerances, one_row, oracle_run
+from helpers import field_errors, fp32_tolerances, fp64_rounding_spread, one_row, oracle_run
 from oracle import mrt
 from paper_1004_5442_amd import workloads as W
 
@@ -20,17 +20,18 @@ if not torch.cuda.is_available():
 
 from paper_1004_5442_amd.batch import Batch  # noqa: E402
 from paper_1004_5442_amd.lib import MRTError, UnstableError  # noqa: E402
+from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
 
 TUBE_WIDTH = 248      # columns one block stores (256 less one per step on either side)
 
 
-def _tubes(sizes, seed=0):
+def _tubes(sizes, seed=0, ny=4):
     """Shock tubes of the given lengths: one block and its edges (1, 3,
     247, 248, 249), two and three blocks with ragged ends."""
     out = []
     for k, nx in enumerate(sizes):
-        c = W.tube_batch(1, seed=seed + k, nx_range=(nx, nx))[0]
-        out.append(dataclasses.replace(c, name=f"tube_nx{nx}"))
+        c = W.tube_batch(1, seed=seed + k, nx_range=(nx, nx), ny=ny)[0]
+        out.append(dataclasses.replace(c, name=f"tube_nx{nx}_ny{ny}"))
     return out
 
 
@@ -87,20 +88,113 @@ def test_tube_march_across_graph_replays_and_step_counts():
             assert np.array_equal(tube.populations(i), one.populations(i)), (n, i)
 
 
+@pytest.mark.parametrize("ny", [1, 2, 4])
+def test_tube_march_fp64_matches_oracle_and_single_steps(ny):
+    """FP64 storage, tubes of one, two and four rows (one to three blocks),
+    13 steps per call over three calls: against the oracle at 1e-12 of the
+    population scale and against one step per pass to rounding order
+    (1e-13: the FP64 collision may fuse products into FMAs differently in
+    the two kernels)."""
+    cases = _tubes([3, TUBE_WIDTH, TUBE_WIDTH + 1, 600], seed=7, ny=ny)
+    one = Batch(cases, "fp64")
+    tube = Batch(cases, "fp64")
+    tube.set_steps_per_pass(4)
+    assert tube.steps_per_pass() == (4, ny)
+    for call in range(3):
+        print(f"call {call} fp64 ny {ny}", flush=True)
+        one.step(13)
+        tube.step(13)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 39)
+        got = tube.populations(i)
+        err = float(np.max(np.abs(got - want)) / np.abs(want).max())
+        d = float(np.max(np.abs(got - one.populations(i))) / np.abs(want).max())
+        print(c.name, "vs oracle", err, "vs one step per pass", d, flush=True)
+        assert err <= 1e-12, (c.name, err)
+        assert d <= 1e-13, (c.name, d)
+
+
+@pytest.mark.parametrize("ny", [1, 2])
+def test_tube_march_one_and_two_rows_fp32(ny):
+    """Tubes of one and two periodic rows in FP32 storage with FP64
+    collision: against the oracle (the stated 1e-5 or twice the
+    FP32-storage error) and against one step per pass (two FP32 ulps)."""
+    cases = _tubes([200, TUBE_WIDTH + 1, 745], seed=4, ny=ny)
+    one = Batch(cases, "fp32_eq64")
+    tube = Batch(cases, "fp32_eq64")
+    tube.set_steps_per_pass(4)
+    one.step(41)
+    tube.step(41)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 41)
+        err = field_errors(tube.moments(i), mrt.macroscopic(want, p.b))
+        tol = fp32_tolerances(c, 41, want)
+        a, b = tube.populations(i), one.populations(i)
+        d = float(np.max(np.abs(a - b)) / np.abs(b).max())
+        print(c.name, err, "vs one step per pass", d, flush=True)
+        assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+        assert d <= 2.4e-7, (c.name, d)
+
+
 def test_tube_march_rejected_outside_its_cover():
-    """FP64 storage, an instance that is not a four-row periodic tube, or
-    non-equilibrium x sides: four steps per pass are refused."""
+    """Instances of other heights, mixed heights in one batch, or
+    non-equilibrium x sides: four steps per pass are refused (batch and
+    single grid); a 2D grid too."""
     tubes = _tubes([300])
-    with pytest.raises(MRTError):
-        Batch(tubes, "fp64").set_steps_per_pass(4)
-    eight = dataclasses.replace(W.tube_batch(1, seed=1, nx_range=(300, 300), ny=8)[0])
+    eight = W.tube_batch(1, seed=1, nx_range=(300, 300), ny=8)[0]
     with pytest.raises(MRTError):
         Batch(tubes + [eight], "fp32_eq64").set_steps_per_pass(4)
+    two = _tubes([300], ny=2)
+    with pytest.raises(MRTError):
+        Batch(tubes + two, "fp64").set_steps_per_pass(4)
     outflow = dataclasses.replace(tubes[0], bc=("eq", "outflow", "periodic", "periodic"))
     with pytest.raises(MRTError):
         Batch([outflow], "fp32_eq64").set_steps_per_pass(4)
     with pytest.raises(MRTError):
         Batch(tubes, "fp32_eq64").set_steps_per_pass(3)
+    s = solver_for_case(eight, "fp64")
+    with pytest.raises(MRTError):
+        s.set_steps_per_pass(4)
+    s.close()
+    s = solver_for_case(W.riemann2d(n=64, seed=0), "fp32_eq64")
+    with pytest.raises(MRTError):
+        s.set_steps_per_pass(4)
+    s.close()
+
+
+def test_single_grid_sod_tube_fp64_by_the_tube_march():
+    """The plain method's Sod tube (400 x 4, FP64, fixed ends, periodic in
+    y) on a single grid, 1000 steps by the tube march: the fields against
+    the oracle at 1e-12, as with one step per pass."""
+    case = W.sod_tube()
+    want, p = oracle_run(case, case.nsteps)
+    s = solver_for_case(case, "fp64")
+    s.set_steps_per_pass(4)
+    assert s.steps_per_pass() == (4, 4)
+    s.step(case.nsteps)
+    err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
+    s.close()
+    print("sod fp64 tube march", err, flush=True)
+    assert max(err.values()) < 1e-12, err
+
+
+def test_single_grid_strong_shock_tube_by_the_tube_march():
+    """The paper's strong-shock tube (gamma 7/5, 1100 x 1, FP64, fixed
+    ends), 2002 steps by the tube march (500 passes and two single steps):
+    against the oracle within 1e-12 or four times the oracle's own spread
+    under one-ulp perturbations (the hot supersonic states amplify
+    rounding), the bound of the one-step test of the same case."""
+    case = W.strong_shock_tube(1.4, False, ny=1)
+    want, p = oracle_run(case, 2002)
+    s = solver_for_case(case, "fp64")
+    s.set_steps_per_pass(4)
+    s.step(2002)
+    got = s.populations()
+    s.close()
+    err = float(np.max(np.abs(got - want)) / np.abs(want).max())
+    tol = max(1e-12, 4.0 * fp64_rounding_spread(case, 2002, want))
+    print("strong shock tube march", err, "tolerance", tol, flush=True)
+    assert err <= tol
 
 
 def test_tube_march_reports_unhealthy_cells():
