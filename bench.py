@@ -343,9 +343,9 @@ def roofline(case, precision, r, traffic=None):
         out["traffic_GBs"] = round(traffic / (r["sec"] / r["steps"] * per_pass) / 1e9, 1)
     if per_pass == 2:
         out["note"] = ("two time steps per launch: each launch reads f^n once and writes f^{n+2}, so "
-                       "its HBM traffic (traffic_GBs) is about 0.62 x the per-step algorithmic bytes; "
-                       "that traffic moves at ~4.6 TB/s, near the 4.7-5.3 TB/s that plain streaming "
-                       "reaches on this chip, with the vector ALUs ~56 % busy")
+                       "its HBM traffic (traffic_GBs) is about 0.61 x the per-step algorithmic bytes; "
+                       "that traffic moves at ~4.6-4.7 TB/s, near the 4.7-5.3 TB/s that plain "
+                       "streaming reaches on this chip, with the vector ALUs ~58 % busy")
     return out
 
 
