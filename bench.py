@@ -431,6 +431,21 @@ def extra_legs(head, prec, steps):
     k = max(20, steps // 4)
     k += k & 1
 
+    def device_copy():
+        # the practical streaming ceiling: a plain 1 GiB device-to-device
+        # copy (read + write of 1 GiB each), after the same 0.3 s preheat
+        import torch
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        _preheat(lambda n: [b.copy_(a) for _ in range(n)])
+        n = 20
+        sec = _events_time(torch.cuda.current_stream(), lambda m: [b.copy_(a) for _ in range(m)], n)
+        gbs = 2 * (1 << 30) * n / sec / 1e9
+        del a, b
+        return {"GBs": round(gbs, 1), "fraction_of_peak": round(gbs / HBM_PEAK_GBS, 4),
+                "note": "plain 1 GiB device copy (torch copy_), 2 GiB moved per copy: the rate "
+                        "a pure stream reaches on this box"}
+
     def one_step():
         r1 = time_solver(head, prec, k, 3, tile_rows=HEADLINE_TILE_ROWS, per_pass=1)
         r1["steps"] = k
@@ -506,6 +521,7 @@ def extra_legs(head, prec, steps):
                         "autotuner's steps per pass, 4 = the tube march)"}
 
     return {
+        "device_copy_1gib": device_copy,
         "fp32_eq64_one_step_per_pass": one_step,
         "fp64_same_grid": fp64,
         "fp64_one_step_per_pass": fp64_one_step,
