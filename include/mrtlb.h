@@ -188,7 +188,8 @@ int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
  * in the FP32 storage forms, within a few roundings in FP64):
  * each work item reads f^n once, keeps f^{n+1} in registers and writes
  * f^{n+2}, recomputing f^{n+1} on the two rows above and below its band of
- * `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = 8 to 32 by grid size) and on its
+ * `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = by grid size, 8 to 32 rows in FP32
+ * storage, 8 to 64 in FP64, which runs one block per CU) and on its
  * two edge columns, which halves the memory traffic per step.  An odd last
  * step of mrt_step runs the single-step kernel.  Every precision; the
  * default scheme only (variants set by mrt_set_scheme run one step per
@@ -203,7 +204,7 @@ int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
  * too on such grids.  Synchronises.
  * Errors: MRT_EINVAL (steps not 1, 2 or 4; rows out of range; 4 on another
  * grid). */
-#define MRT_MAX_BAND_ROWS_2 32
+#define MRT_MAX_BAND_ROWS_2 64
 int mrt_set_steps_per_pass(mrt_ctx* ctx, int steps, int rows);
 int mrt_get_steps_per_pass(const mrt_ctx* ctx, int* steps, int* rows);
 

@@ -523,7 +523,7 @@ __global__ __launch_bounds__(256, (step_waves<S, COMP, WALLS>())) void step_kern
 // fixed-equilibrium ghosts are the adjacent f^{n+1} cell, its reflection,
 // and the side's equilibrium.  The f^{n+2} ghost ring is refilled by the
 // ghost pass before the next launch.
-constexpr int kBand2 = 32;
+constexpr int kBand2 = 64;
 
 // The instance pointer made opaque to the compiler, so that the parameters
 // read through it (rates, Lax-Wendroff weights) are loaded again where they

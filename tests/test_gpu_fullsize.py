@@ -1,10 +1,10 @@
 """GPU parity at full size, in the launch configuration the benchmark times.
 
 The 4096^2 shock-bubble grid (FP32 storage: 1.15 GB per population buffer,
-so the kernels take their non-temporal store path, and FP32 storage runs two
-steps per pass by default; the one-step kernel is checked there too) and
-the 1024^2 2D
-Riemann grid (cache-resident, cached stores) run a few steps on the GPU; the
+so the kernels take their non-temporal store path; both precisions run two
+steps per pass by default there, and the one-step kernel is checked too) and
+the 1024^2 2D Riemann grid (cache-resident, cached stores) run a few steps on
+the GPU; the
 oracle evaluates small windows around sampled cells (the shock front, the
 bubble edge, every kind of boundary, the corners) one by one
 (``mrt.evolve_window``: a window of the initial fields grown by one cell per
@@ -29,6 +29,7 @@ if not torch.cuda.is_available():
 from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
 
 HEADLINE_BAND_ROWS_2 = 32    # the benchmark's 4096^2 FP32 run: two steps per pass, 32-row bands
+FP64_BAND_ROWS_2 = 64        # its FP64 run (the library's default for FP64 at this size)
 HEADLINE_TILE_ROWS = 8       # its one-step-per-pass runs (FP64, and FP32 for comparison)
 NSTEPS = 6                   # steps before sampling (window margin = NSTEPS)
 PATCH = 6                    # sampled patch: PATCH x PATCH cells
@@ -105,6 +106,7 @@ def shock_bubble_centres(n):
 
 @pytest.mark.parametrize("precision,per_pass,rows", [("fp32_eq64", 2, HEADLINE_BAND_ROWS_2),
                                                      ("fp32_eq64", 1, HEADLINE_TILE_ROWS),
+                                                     ("fp64", 2, FP64_BAND_ROWS_2),
                                                      ("fp64", 1, HEADLINE_TILE_ROWS)])
 def test_shock_bubble_4096_sampled(precision, per_pass, rows):
     n = 4096
@@ -112,10 +114,11 @@ def test_shock_bubble_4096_sampled(precision, per_pass, rows):
     print(f"case {case.name} {precision} {per_pass} steps per pass, {rows}-row bands", flush=True)
     s = solver_for_case(case, precision)
     if per_pass == 2:
+        if precision == "fp64":
+            assert s.steps_per_pass() == (2, FP64_BAND_ROWS_2)    # the default here
         s.set_steps_per_pass(2, rows)
     else:
-        if precision != "fp64":
-            s.set_steps_per_pass(1, 0)
+        s.set_steps_per_pass(1, 0)
         s.set_tile(rows)
     s.step(NSTEPS)
     s.sync()
@@ -193,16 +196,18 @@ def test_riemann2d_1024_sampled_after_100_steps(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32_eq64"])
 def test_shock_bubble_4096_sampled_after_100_steps(precision):
     """The shock-bubble workload at 4096^2 in the launch the benchmark times
-    for both precisions (two steps per pass, 32-row bands), after 100 steps,
+    for each precision (two steps per pass, 32-row bands in FP32 storage,
+    64-row in FP64), after 100 steps,
     on patches at the shock front, where it meets a wall, on the bubble edge
     and at the inflow and outflow sides, against the oracle's windowed
     evaluation (windows of up to 206 x 206 cells)."""
     n, nsteps = 4096, 100
     case = W.shock_bubble(n=n)
     print(f"case {case.name} {precision} two steps per pass, {nsteps} steps", flush=True)
+    rows = FP64_BAND_ROWS_2 if precision == "fp64" else HEADLINE_BAND_ROWS_2
     s = solver_for_case(case, precision)
-    s.set_steps_per_pass(2, HEADLINE_BAND_ROWS_2)
-    assert s.steps_per_pass() == (2, HEADLINE_BAND_ROWS_2)
+    s.set_steps_per_pass(2, rows)
+    assert s.steps_per_pass() == (2, rows)
     s.step(nsteps)
     s.sync()
     bx, by, br = int(0.25 * n), n // 2, int(0.1 * n)

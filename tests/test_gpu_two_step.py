@@ -188,7 +188,7 @@ def test_rejected_settings():
     from paper_1004_5442_amd.lib import MRTError
     case = smooth_case(64, 5, BC_SETS[0])
     s = solver_for_case(case, "fp32_eq64")
-    for steps, rows in ((3, 0), (0, 0), (2, 33), (2, -1)):
+    for steps, rows in ((3, 0), (0, 0), (2, 65), (2, -1)):
         with pytest.raises(MRTError):
             s.set_steps_per_pass(steps, rows)
     s.set_steps_per_pass(2, 32)                 # accepted: clamped to the 5 rows
