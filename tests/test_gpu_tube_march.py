@@ -251,3 +251,37 @@ def test_full_batch_512_tubes_tube_march(which):
     tol = fp32_tolerances(c1, 1000, want)
     print(which, c.name, f"nx {c.nx}", "err", err, "tol", tol, flush=True)
     assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+
+
+def test_tube_march_prepared_graphs_and_autotuned_single_grid():
+    """Graphs captured ahead of the steps (prepare, as the benchmark does)
+    replay the same passes as graphs captured on first use (bit for bit);
+    and the single-grid autotuner, which times the tube march on a tube,
+    leaves a launch whose steps equal single steps to rounding order (on
+    the paper's strong-shock tube, whose hot supersonic states amplify
+    rounding: 1e-12 or four times the oracle's own one-ulp spread)."""
+    cases = _tubes([300, 700], seed=8)
+    a, b = Batch(cases, "fp32_eq64"), Batch(cases, "fp32_eq64")
+    a.set_steps_per_pass(4)
+    b.set_steps_per_pass(4)
+    a.prepare(258)
+    a.step(258)
+    b.step(258)
+    for i in range(len(cases)):
+        assert np.array_equal(a.populations(i), b.populations(i)), i
+    case = W.strong_shock_tube(1.4, False, ny=1)
+    tuned = solver_for_case(case, "fp64")
+    tuned.autotune(4)
+    print("autotuned", tuned.steps_per_pass(), tuned.tile(), flush=True)
+    one = solver_for_case(case, "fp64")
+    one.set_steps_per_pass(1, 0)
+    tuned.step(202)
+    one.step(202)
+    got, ref = tuned.populations(), one.populations()
+    d = float(np.max(np.abs(got - ref)) / np.abs(ref).max())
+    want, _ = oracle_run(case, 202)
+    tol = max(1e-12, 4.0 * fp64_rounding_spread(case, 202, want))
+    print("autotuned against single steps", d, "tolerance", tol, flush=True)
+    assert d <= tol
+    tuned.close()
+    one.close()
