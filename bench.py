@@ -482,6 +482,18 @@ def extra_legs(head, prec, steps):
                     "note": "fits the 256 MB Infinity Cache: effective, not HBM, bandwidth"}
         return run
 
+    def stripe():
+        # one GPU's share of the headline grid in the stripe decomposition at
+        # eight GPUs (4096 x 512 rows of the same workload; 134 MB per state:
+        # cache-resident), in the autotuner's launch; the halo exchange that
+        # would replace the reflecting ghost pass is not modelled
+        c = W.shock_bubble(n=4096, ny=512)
+        rr = time_solver(c, prec, 2 * k, 5)
+        rr["steps"] = 2 * k
+        return {"mlups": round(rr["mlups"], 1), "steps_per_pass": rr["per_pass"],
+                "band_rows": rr["band_rows"], "effective_GBs": roofline(c, prec, rr)["achieved"],
+                "note": "4096 x 512: one GPU's share at eight; fits the 256 MB Infinity Cache"}
+
     def variants():
         out = {}
         for name, sch, bps in (("split", {"split": True}, 256), ("lw_cross", {"lw_cross": True}, 128),
@@ -527,6 +539,7 @@ def extra_legs(head, prec, steps):
         "fp64_same_grid": fp64,
         "fp64_one_step_per_pass": fp64_one_step,
         "fp32_same_grid": fp32,
+        "stripe_4096x512_fp32_eq64": stripe,
         "riemann2d_1024_fp32_eq64": riemann("fp32_eq64"),
         "riemann2d_1024_fp64": riemann("fp64"),
         "scheme_variants_4096_fp32_eq64": variants,
