@@ -183,19 +183,20 @@ def time_solver(case, precision, steps, warmup, autotune=True, tile_rows=0, sche
             "per_pass": pp[0], "band_rows": pp[1], "preheat_steps": pre}
 
 
-def time_batch(steps, warmup):
+def time_batch(steps, warmup, precision="fp32_eq64"):
     """The batched form: 512 seeded shock tubes (nx 200..4000, ny 4), FP32
-    populations with FP64 collision, graph-captured passes in the launch the
-    batch autotuner picks (the tube march, four steps per pass, on this
-    batch); the step counts are rounded up to whole passes."""
+    populations with FP64 collision (or the given precision), graph-captured
+    passes in the launch the batch autotuner picks (the tube march, four
+    steps per pass, on this batch); the step counts are rounded up to whole
+    passes."""
     import torch
 
     from paper_1004_5442_amd import workloads as W
     from paper_1004_5442_amd.batch import Batch
     cases = W.tube_batch(512, seed=0)
-    b = Batch(cases, "fp32_eq64")
+    b = Batch(cases, precision)
     b.autotune(4)
-    heat = Batch(cases, "fp32_eq64")
+    heat = Batch(cases, precision)
     heat.set_tile(*b.tile())
     k, r = b.steps_per_pass()
     heat.set_steps_per_pass(k, r if k == 2 else 0)
@@ -216,7 +217,7 @@ def time_batch(steps, warmup):
             "ms_per_step": round(1e3 * sec / steps, 4), "steps": steps, "tile_rows": tile[0],
             "kernel": {1: "step_kernel", 2: "step2_kernel", 4: "tube_kernel"}[pp[0]],
             "steps_per_pass": pp[0], "band_rows": pp[1], "preheat_steps": pre,
-            "roofline_frac": round(cells * 128 * steps / sec / 1e9 / HBM_PEAK_GBS, 4)}
+            "roofline_frac": round(cells * BYTES_PER_SITE[precision] * steps / sec / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def time_adjoint_large(n, steps):
@@ -548,6 +549,7 @@ def extra_legs(head, prec, steps):
         "paper_riemann2d_500_fp64": paper_riemann2d,
         "strong_shock_tube_1100_fp64": strong_shock,
         "batched_512_tubes": lambda: time_batch(max(50, steps // 2), 5),
+        "batched_512_tubes_fp64": lambda: time_batch(max(50, steps // 2), 5, "fp64"),
         "adjoint_256": lambda: time_adjoint(100),
         "adjoint_2048": lambda: time_adjoint_large(2048, 20),
     }
