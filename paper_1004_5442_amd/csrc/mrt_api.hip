@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mrt_dual.h"
@@ -247,7 +248,10 @@ hipError_t run_graphs(GraphCache& cache, int& cur, int n, hipStream_t stream, En
         }
         int c = start;
         for (int k = 0; k < steps && e == hipSuccess; ++k) {
-            e = enqueue(c, cap);
+            if constexpr (std::is_invocable_v<Enqueue, int, hipStream_t, int>)
+                e = enqueue(c, cap, k);
+            else
+                e = enqueue(c, cap);
             c ^= 1;
         }
         hipGraph_t graph = nullptr;
@@ -678,10 +682,12 @@ static int step_impl(mrt_ctx* c, int n, bool launch) {
     }
     if (c->per_pass == 2 && c->scheme == 0) {
         // two steps per pass; an odd last step by the single-step kernel.
-        // Neither writes the reflecting-wall ghosts of its output here: the
-        // ghost pass refreshes them before every launch
-        auto enqueue2 = [&](int cur, hipStream_t st) -> hipError_t {
-            if (reflect) {
+        // The two-step kernel writes the reflecting y-wall ghosts of its
+        // output, so the ghost pass runs before the first pass of a call or
+        // graph only, unless an x side reflects (then before every pass)
+        const bool xwall = c->bc[0] == MRT_BC_REFLECT || c->bc[1] == MRT_BC_REFLECT;
+        auto enqueue2 = [&](int cur, hipStream_t st, int k) -> hipError_t {
+            if (reflect && (k == 0 || xwall)) {
                 const hipError_t e = mrt::k_ghost(c->prec, c->d_inst, 1, perim, c->f[cur], 1, st);
                 if (e != hipSuccess) return e;
             }
@@ -701,7 +707,7 @@ static int step_impl(mrt_ctx* c, int n, bool launch) {
             // plain launches, one per pass (the autotuner times these)
             if (launch)
                 for (int k = 0; k < pairs; ++k) {
-                    HIPTRY(enqueue2(c->cur, c->stream));
+                    HIPTRY(enqueue2(c->cur, c->stream, k));
                     c->cur ^= 1;
                 }
         } else if (pairs > 1) {
@@ -856,7 +862,7 @@ int mrt_set_steps_per_pass(mrt_ctx* c, int steps, int rows) {
     c->graphs.clear();
     c->graphs2.clear();
     c->graphs4.clear();
-    // the two-step path leaves the reflecting ghosts of the current state
+    // the two-step path can leave the reflecting ghosts of the current state
     // stale; the single-step kernel expects them current
     if (c->params_set && c->fields_set) {
         const int rc = fill_ghosts(c);
@@ -908,7 +914,7 @@ int mrt_autotune(mrt_ctx* c, int steps) {
     if (!c->params_set || !c->fields_set) return ctx_fail(c, MRT_ESTATE, "params and fields must be set");
     if (steps < 1) steps = 4;
     // the saved state must carry current reflecting-wall ghosts (after
-    // two-step passes they are stale), whichever kernel is chosen
+    // two-step passes they can be stale), whichever kernel is chosen
     {
         const int rc = fill_ghosts(c);
         if (rc != MRT_OK) return rc;
@@ -1213,6 +1219,7 @@ struct mrt_batch {
     long long total_cells = 0, total_elems = 0, max_cells = 0;
     int max_perim = 0;
     bool any_reflect = false;
+    bool any_xwall = false;                 // some instance has a reflecting x side
     void* f[2] = {nullptr, nullptr};
     int cur = 0;
     Inst* d_insts = nullptr;
@@ -1329,6 +1336,7 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
         I.plane = plane_for(d.nx);
         b->max_perim = std::max(b->max_perim, 2 * (d.nx + d.ny));
         b->any_reflect = b->any_reflect || has_kind(d.bc, MRT_BC_REFLECT);
+        b->any_xwall = b->any_xwall || d.bc[0] == MRT_BC_REFLECT || d.bc[1] == MRT_BC_REFLECT;
         I.off = off;
         std::string e;
         if (fill_inst(I, d.nx, d.ny, d.bc, &d.params, e) != MRT_OK) {
@@ -1421,14 +1429,16 @@ static int batch_step_impl(mrt_batch* b, int n, bool launch) {
         return MRT_OK;
     }
     if (b->per_pass == 2) {
-        // two steps per pass, an odd last step by the single-step kernel;
-        // the reflecting-wall ghosts are refilled before every launch
+        // two steps per pass, an odd last step by the single-step kernel.
+        // The two-step kernel writes the reflecting y-wall ghosts of its
+        // output: the ghost pass runs before the first pass of a graph, and
+        // before every pass only when some instance has a reflecting x side
         auto ghosts = [&](int cur, hipStream_t st) -> hipError_t {
             return b->any_reflect ? mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[cur], 1, st)
                                   : hipSuccess;
         };
-        auto enqueue2 = [&](int cur, hipStream_t st) -> hipError_t {
-            const hipError_t e = ghosts(cur, st);
+        auto enqueue2 = [&](int cur, hipStream_t st, int k) -> hipError_t {
+            const hipError_t e = k == 0 || b->any_xwall ? ghosts(cur, st) : hipSuccess;
             if (e != hipSuccess) return e;
             return mrt::k_step2(b->prec, b->d_insts, b->d_items2, b->nitems2, b->f[cur], b->f[1 - cur],
                                 b->d_health, 0, b->nt, b->wrap4, st);
@@ -1529,7 +1539,7 @@ int mrt_batch_set_steps_per_pass(mrt_batch* b, int steps, int rows) {
     b->graphs.clear();
     b->graphs2.clear();
     b->graphs4.clear();
-    // the two-step path leaves the reflecting ghosts of the current state
+    // the two-step path can leave the reflecting ghosts of the current state
     // stale; the single-step kernel with in-kernel walls expects them current
     if (b->any_reflect)
         HIPTRY(mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[b->cur], 1, b->stream));
@@ -1556,7 +1566,7 @@ int mrt_batch_autotune(mrt_batch* b, int steps) {
     std::string& ctx_err = b->err;
     if (steps < 1) steps = 8;
     // the saved state must carry current reflecting-wall ghosts (after
-    // two-step passes they are stale), whichever kernel is chosen
+    // two-step passes they can be stale), whichever kernel is chosen
     if (b->any_reflect)
         HIPTRY(mrt::k_ghost(b->prec, b->d_insts, b->count, b->max_perim, b->f[b->cur], 1, b->stream));
     const size_t bytes = size_t(b->total_elems) * elem_size(b->prec);

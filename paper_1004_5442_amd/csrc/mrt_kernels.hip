@@ -893,6 +893,29 @@ __device__ __forceinline__ void step2_block(ConstInst* __restrict__ P, int x0, i
         if (y > y1) break;
         body(D, A, B, Cw, F, G, H, y); ++y;
     }
+    // Reflecting y-wall ghosts of f^{n+2} (section (d)), after the march
+    // rather than in it (inlined in the march's row rotations they cost the
+    // loop 5 %): a band holding a wall row reads back the elements each lane
+    // stored itself (its own earlier stores to the same addresses, so the
+    // reads see them) and writes their reflection into the ghost row, so the
+    // next launch needs no ghost pass for y walls.  A one-row grid writes
+    // both ghost rows from its one row.
+    const bool ref_lo = P->bc[YLO] == BC_REFLECT && y0 == 0;
+    const bool ref_hi = P->bc[YHI] == BC_REFLECT && y1 == ny;
+    if (ref_lo || ref_hi) {
+#pragma unroll 1
+        for (int side = 0; side < 2; ++side) {
+            if (!(side == 0 ? ref_lo : ref_hi)) continue;
+            const unsigned o = roff(side == 0 ? 0 : ny - 1) + xs;
+            const unsigned og = roff(side == 0 ? -1 : ny) + xs;
+            S v[16], g[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) v[i] = (fo + (long long)i * plane)[o];
+            reflected_eq<C>(v, 1, b, binv, g);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) (fo + (long long)i * plane)[og] = g[i];
+        }
+    }
     if (act && !healthy) atomicOr(health, 1u);
 }
 

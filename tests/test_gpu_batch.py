@@ -113,6 +113,52 @@ def test_two_step_batch_matches_oracle_and_single_step(precision, rows):
         assert d < 1e-6, (c.name, d)
 
 
+def _y_wall_cases():
+    """Reflecting y walls, no reflecting x side: the two-step kernel writes
+    the wall ghosts of its own output, so a graph of passes runs one ghost
+    pass (one-row and one-column instances: both ghost rows come from the
+    same row, or a band holds the whole height)."""
+    return [smooth_case(150, 37, ("eq", "outflow", "reflect", "reflect"), seed=5),
+            smooth_case(70, 1, ("outflow", "outflow", "reflect", "reflect"), seed=6),
+            smooth_case(300, 9, ("periodic", "periodic", "reflect", "eq"), seed=7),
+            smooth_case(1, 12, ("eq", "eq", "reflect", "reflect"), seed=8),
+            smooth_case(260, 70, ("eq", "eq", "outflow", "reflect"), seed=10)]
+
+
+@pytest.mark.parametrize("precision,rows", [("fp64", 4), ("fp64", 32), ("fp32_eq64", 32)])
+def test_two_step_batch_y_walls_only(precision, rows):
+    """Two steps per pass over a batch whose only reflecting sides are y
+    walls: 140 steps per call (a 64-pass graph and a 6-pass graph) over two
+    calls, then 13 (six passes and a one-step pass), against the oracle and
+    the one-step batch (FP64: 1e-12 of the population scale against the
+    oracle, 1e-13 against one step; FP32 storage: the FP32 tolerances and
+    1e-6)."""
+    cases = _y_wall_cases()
+    one = Batch(cases, precision)
+    two = Batch(cases, precision)
+    two.set_steps_per_pass(2, rows)
+    assert two.steps_per_pass() == (2, rows)
+    for n in (140, 140, 13):
+        print(f"{n} steps {precision} rows {rows}", flush=True)
+        one.step(n)
+        two.step(n)
+    for i, c in enumerate(cases):
+        want, p = oracle_run(c, 293)
+        a, b = two.populations(i), one.populations(i)
+        d = float(np.max(np.abs(a - b)) / np.abs(b).max())
+        if precision == "fp64":
+            err = float(np.max(np.abs(a - want)) / np.abs(want).max())
+            print(c.name, "vs oracle", err, "vs one step", d, flush=True)
+            assert err <= 1e-12, (c.name, err)
+            assert d <= 1e-13, (c.name, d)
+        else:
+            err = field_errors(two.moments(i), mrt.macroscopic(want, p.b))
+            tol = fp32_tolerances(c, 293, want)
+            print(c.name, err, "vs one step", d, flush=True)
+            assert all(err[k] < tol[k] for k in err), (c.name, err, tol)
+            assert d < 1e-6, (c.name, d)
+
+
 def test_wrapped_four_row_bands_match_plain_bands():
     """FP32 storage with FP64 collision: bands that are a whole periodic
     height of four rows (f^{n+1} and f^n of their last rows taken from the
