@@ -287,15 +287,24 @@ int mrt_step_checkpointed(mrt_ctx* ctx, void* f, void* f_tmp, int segment, int n
  * step (segment ~ sqrt(N) minimises the memory).
  *   lam      on entry lam^N, on return lam^0
  *   lam_tmp  one more buffer (overwritten)
- *   work     min(segment, nsteps) - 1 state buffers (overwritten)
+ *   work     nwork state buffers (overwritten); nwork >= w = min(segment,
+ *            nsteps) - 1.  With nwork >= 2 w (and two segments or more) the
+ *            next segment's states are recomputed on a second stream of the
+ *            context into the other w buffers while the adjoint steps of the
+ *            current segment run on the context's stream (the two kernels
+ *            share the GPU); the adjoint steps stay in order on one stream,
+ *            so lam and ds are bitwise those of the one-set sweep.  The call
+ *            returns with all of its work ordered before later work on the
+ *            context's stream.
  *   ds       16 device doubles, accumulated (the per-cell contributions of
  *            all steps are summed per wave first and reduced once, so ds
  *            equals the sum of nsteps mrt_adjoint_step calls up to rounding
  *            order, and is bitwise reproducible)
  * Buffers as for mrt_step_checkpointed (the checkpoints are only read).
- * Periodic grids only (MRT_EINVAL otherwise).  Asynchronous. */
+ * Periodic grids only (MRT_EINVAL otherwise; also for nwork < w or NULL,
+ * lam-aliased work buffers).  Asynchronous. */
 int mrt_adjoint_sweep(mrt_ctx* ctx, const void* const* checkpoints, int segment, int nsteps,
-                      void* const* work, void* lam, void* lam_tmp, double* ds);
+                      void* const* work, int nwork, void* lam, void* lam_tmp, double* ds);
 
 /* One forward step between explicit device buffers (storage precision,
  * padded layout), without touching the context's own buffers: used to

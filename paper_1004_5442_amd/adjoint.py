@@ -10,9 +10,10 @@ Backward: lam^N = g_rho (every population), then per step, newest first,
 The states f^n needed by the backward pass are not all kept: every K-th
 state (K ~ sqrt(N)) is stored in the forward pass (``mrt_step_checkpointed``,
 which writes it in place), and each segment of K states is recomputed from
-its checkpoint just before its adjoint steps (``mrt_adjoint_sweep``; both
-loops run in the library), so memory is O(sqrt(N)) states for one extra
-forward pass.  Keeping every state instead (segment = 1) measured slower on
+its checkpoint (``mrt_adjoint_sweep``; both loops run in the library, the
+recomputation of the next segment on a second stream beside the adjoint
+steps of the current one), so memory is O(sqrt(N)) states (the checkpoints
+and two segments) for one extra forward pass.  Keeping every state instead (segment = 1) measured slower on
 the 256^2 / 500-step workload (4.1 x the forward run against 3.3 x): its 500
 states stream through HBM, while the sqrt(N) working set stays in the 256 MB
 Infinity Cache.  Periodic grids only.
@@ -68,8 +69,10 @@ class DensityMap(torch.autograd.Function):
         lam, lam2 = solver.empty_state(), solver.empty_state()
         solver.density_adjoint(g_rhoN.detach().to(torch.float64).contiguous(), lam)
         ds = torch.zeros(16, dtype=torch.float64, device=rho0d.device)
-        # one segment's recomputed states, overwritten by every segment
-        work = [solver.empty_state() for _ in range(min(K, N) - 1)]
+        # recomputed states of two segments: the library recomputes the next
+        # segment on a second stream while the adjoint steps read the other
+        w = max(0, min(K, N) - 1)
+        work = [solver.empty_state() for _ in range(2 * w if N > K else w)]
         solver.adjoint_sweep(ctx.checkpoints, K, N, work, lam, lam2, ds)
         del work
         zero = torch.zeros_like(rho0d)

@@ -375,6 +375,11 @@ struct mrt_ctx {
     double* d_scratch = nullptr;     // the static scratch on this context's device
     std::string scratch_err;         // why d_scratch could not be resolved
     unsigned* d_health = nullptr;
+    // second stream of the adjoint sweep (recomputation of the next segment
+    // beside the adjoint steps of the current one) and its events, made on
+    // first use
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_rec[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
     bool params_set = false, fields_set = false;
     std::string err;
 };
@@ -1041,6 +1046,12 @@ void mrt_destroy(mrt_ctx* c) {
     if (c->d_stage) (void)hipFree(c->d_stage);
     if (c->d_partial) (void)hipFree(c->d_partial);
     if (c->d_health) (void)hipFree(c->d_health);
+    if (c->aux) {
+        (void)hipStreamSynchronize(c->aux);
+        (void)hipStreamDestroy(c->aux);
+    }
+    for (hipEvent_t e : {c->ev_fork, c->ev_rec[0], c->ev_rec[1], c->ev_adj[0], c->ev_adj[1]})
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -1124,43 +1135,111 @@ int mrt_step_checkpointed(mrt_ctx* c, void* f, void* f_tmp, int segment, int nst
     return MRT_OK;
 }
 
+// The sweep's second stream (default priority, like every stream here) and
+// its events.
+static int ensure_aux_stream(mrt_ctx* c) {
+    std::string& ctx_err = c->err;
+    if (c->aux) return MRT_OK;
+    hipStream_t st = nullptr;
+    HIPTRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    c->aux = st;
+    for (hipEvent_t* e : {&c->ev_fork, &c->ev_rec[0], &c->ev_rec[1], &c->ev_adj[0], &c->ev_adj[1]})
+        HIPTRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    return MRT_OK;
+}
+
 int mrt_adjoint_sweep(mrt_ctx* c, const void* const* checkpoints, int segment, int nsteps,
-                      void* const* work, void* lam, void* lam_tmp, double* ds) {
+                      void* const* work, int nwork, void* lam, void* lam_tmp, double* ds) {
     if (!c) return MRT_EINVAL;
     std::string& ctx_err = c->err;
     if (!c->params_set) return ctx_fail(c, MRT_ESTATE, "set_params first");
     if (!all_periodic(c)) return ctx_fail(c, MRT_EINVAL, "adjoint needs periodic boundaries");
     if (c->scheme) return ctx_fail(c, MRT_EINVAL, "the adjoint is of the default scheme only");
-    if (!lam || !lam_tmp || lam == lam_tmp || !ds || segment < 1 || nsteps < 0 ||
-        (nsteps > 0 && !checkpoints) || (segment > 1 && nsteps > 1 && !work))
+    if (!lam || !lam_tmp || lam == lam_tmp || !ds || segment < 1 || nsteps < 0 || nwork < 0 ||
+        (nsteps > 0 && !checkpoints))
         return ctx_fail(c, MRT_EINVAL, "bad adjoint-sweep arguments");
     const int nck = (nsteps + segment - 1) / segment;
     for (int k = 0; k < nck; ++k)
         if (!checkpoints[k]) return ctx_fail(c, MRT_EINVAL, "missing checkpoint");
-    const int nwork = std::min(segment, nsteps) - 1;
-    for (int j = 0; j < nwork; ++j)
+    // w recomputed states per segment; two sets of them let the next
+    // segment's recomputation run beside the current segment's adjoint steps
+    const int w = std::max(0, std::min(segment, nsteps) - 1);
+    if (nwork < w) return ctx_fail(c, MRT_EINVAL, "fewer work buffers than min(segment, nsteps) - 1");
+    const int sets = (w > 0 && nck > 1 && nwork >= 2 * w) ? 2 : 1;
+    if (w > 0 && !work) return ctx_fail(c, MRT_EINVAL, "bad adjoint-sweep arguments");
+    for (int j = 0; j < sets * w; ++j)
         if (!work[j] || work[j] == lam || work[j] == lam_tmp)
             return ctx_fail(c, MRT_EINVAL, "work buffers must be distinct from lam and lam_tmp");
+    if (sets == 2) {
+        const int rc = ensure_aux_stream(c);
+        if (rc != MRT_OK) return rc;
+    }
+    auto set_of = [&](int seg) { return sets == 2 ? (seg & 1) : 0; };
+    // f^{start + j} of segment seg: its checkpoint for j = 0, else a work buffer
+    auto state = [&](int seg, int j) -> const void* {
+        return j == 0 ? checkpoints[seg] : work[set_of(seg) * w + j - 1];
+    };
+    // f^{start + 1} .. f^{stop - 1} of segment seg, one step each as
+    // mrt_step_buffers takes it on a periodic grid (no ghost ring to refill)
+    auto recompute = [&](int seg, hipStream_t st) -> hipError_t {
+        const int start = seg * segment, stop = std::min(nsteps, start + segment);
+        for (int j = 1; j < stop - start; ++j) {
+            const hipError_t e = mrt::k_step(c->prec, c->d_inst, c->d_items, c->nitems, state(seg, j - 1),
+                                             const_cast<void*>(state(seg, j)), c->d_health, c->grid, c->nt,
+                                             c->walls, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     void* cur = lam;
     void* nxt = lam_tmp;
     // the rate-gradient partial rows of all steps are summed in place and
     // reduced into ds once, after the last step
     bool first = true;
-    for (int seg = nck - 1; seg >= 0; --seg) {
+    auto adjoint_steps = [&](int seg) -> hipError_t {
         const int start = seg * segment, stop = std::min(nsteps, start + segment);
-        // f^{start + j}: the checkpoint for j = 0, else work[j - 1]
-        auto state = [&](int j) -> const void* { return j == 0 ? checkpoints[seg] : work[j - 1]; };
-        for (int j = 1; j < stop - start; ++j) {
-            const int rc = mrt_step_buffers(c, state(j - 1), work[j - 1]);
-            if (rc != MRT_OK) return rc;
-        }
         for (int n = stop - 1; n >= start; --n) {
-            HIPTRY(mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, cur,
-                                  state(n - start), nxt, c->d_partial, !first,
-                                  n == 0 ? ds : nullptr, c->nt, c->stream));
+            const hipError_t e = mrt::k_adjoint(c->prec, c->d_inst, c->d_items_adj, c->nitems_adj, cur,
+                                                state(seg, n - start), nxt, c->d_partial, !first,
+                                                n == 0 ? ds : nullptr, c->nt, c->stream);
+            if (e != hipSuccess) return e;
             first = false;
             std::swap(cur, nxt);
         }
+        return hipSuccess;
+    };
+    if (sets == 1) {
+        for (int seg = nck - 1; seg >= 0; --seg) {
+            HIPTRY(recompute(seg, c->stream));
+            HIPTRY(adjoint_steps(seg));
+        }
+    } else {
+        // segment seg's states are recomputed on the second stream into set
+        // seg & 1 while the adjoint steps of segment seg + 1 read the other
+        // set on the context's stream.  ev_rec[s]: set s holds its segment's
+        // states; ev_adj[s]: the adjoint steps reading set s are done, so it
+        // may be overwritten.  The adjoint steps themselves stay in order on
+        // one stream: lam and ds are those of the one-stream sweep.
+        HIPTRY(hipEventRecord(c->ev_fork, c->stream));
+        HIPTRY(hipStreamWaitEvent(c->aux, c->ev_fork, 0));
+        bool read_issued[2] = {false, false};
+        HIPTRY(recompute(nck - 1, c->aux));
+        HIPTRY(hipEventRecord(c->ev_rec[set_of(nck - 1)], c->aux));
+        for (int seg = nck - 1; seg >= 0; --seg) {
+            if (seg >= 1) {
+                const int s2 = set_of(seg - 1);
+                if (read_issued[s2]) HIPTRY(hipStreamWaitEvent(c->aux, c->ev_adj[s2], 0));
+                HIPTRY(recompute(seg - 1, c->aux));
+                HIPTRY(hipEventRecord(c->ev_rec[s2], c->aux));
+            }
+            const int s1 = set_of(seg);
+            HIPTRY(hipStreamWaitEvent(c->stream, c->ev_rec[s1], 0));
+            HIPTRY(adjoint_steps(seg));
+            HIPTRY(hipEventRecord(c->ev_adj[s1], c->stream));
+            read_issued[s1] = true;
+        }
+        // the context's stream waited for the last recomputation (segment 0)
+        // before its adjoint steps: nothing of the sweep is left on aux
     }
     if (cur != lam) {
         const size_t bytes = size_t(mrt_population_bytes(c->nx, c->ny, c->prec));

@@ -78,7 +78,7 @@ _proto = {
     "mrt_step_buffers": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mrt_step_checkpointed": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, POINTER(c_void_p)]),
     "mrt_adjoint_sweep": (c_int, [c_void_p, POINTER(c_void_p), c_int, c_int, POINTER(c_void_p),
-                                  c_void_p, c_void_p, c_void_p]),
+                                  c_int, c_void_p, c_void_p, c_void_p]),
     "mrt_density": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mrt_density_adjoint": (c_int, [c_void_p, c_void_p, c_void_p]),
     "mrt_init_adjoint": (c_int, [c_void_p] + [c_void_p] * 9),

@@ -184,9 +184,12 @@ class Solver:
     def adjoint_sweep(self, checkpoints: Sequence[torch.Tensor], segment: int, nsteps: int,
                       work: Sequence[torch.Tensor], lam: torch.Tensor, lam_tmp: torch.Tensor,
                       ds: torch.Tensor):
+        """work: min(segment, nsteps) - 1 state buffers, or twice as many to
+        recompute the next segment on a second stream beside the adjoint
+        steps (same results)."""
         ck = (c_void_p * max(1, len(checkpoints)))(*[t.data_ptr() for t in checkpoints])
         wk = (c_void_p * max(1, len(work)))(*[t.data_ptr() for t in work])
-        self._check(L.raw().mrt_adjoint_sweep(self._h, ck, int(segment), int(nsteps), wk,
+        self._check(L.raw().mrt_adjoint_sweep(self._h, ck, int(segment), int(nsteps), wk, len(work),
                                               _dev_ptr(lam), _dev_ptr(lam_tmp), _dev_ptr(ds)))
 
     def init_buffer(self, rho, ux, uy, T, f: torch.Tensor):

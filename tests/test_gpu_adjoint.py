@@ -139,12 +139,14 @@ def test_checkpoint_segment_does_not_change_gradient():
     assert np.array_equal(grads[0], grads[1]) and np.array_equal(grads[1], grads[2])
 
 
+@pytest.mark.parametrize("sets", [1, 2])
 @pytest.mark.parametrize("nsteps,segment", [(13, 4), (12, 4), (5, 9), (1, 1), (7, 1), (8, 2)])
-def test_native_checkpoint_loops_equal_explicit_steps(nsteps, segment):
+def test_native_checkpoint_loops_equal_explicit_steps(nsteps, segment, sets):
     """mrt_step_checkpointed / mrt_adjoint_sweep against the same work done
     one mrt_step_buffers / mrt_adjoint_step call at a time (states and lam
     bitwise, ds to rounding order), for odd and even step counts and a
-    segment longer than the run."""
+    segment longer than the run; with one set of work buffers, and with two
+    (the next segment recomputed on the second stream)."""
     rho, T, s, dt, dx, dy = _small_case(70, 9, seed=2)
     ny, nx = rho.shape
     sv = Solver(nx, ny, "fp32_eq64")
@@ -176,7 +178,7 @@ def test_native_checkpoint_loops_equal_explicit_steps(nsteps, segment):
         lam, lam2 = lam2, lam
     # native sweep
     lamS, lamT = _padded(sv, lamN), sv.empty_state()
-    work = [sv.empty_state() for _ in range(min(segment, nsteps) - 1)]
+    work = [sv.empty_state() for _ in range(sets * (min(segment, nsteps) - 1))]
     ds = torch.zeros(16, dtype=torch.float64, device="cuda")
     sv.adjoint_sweep(ck, segment, nsteps, work, lamS, lamT, ds)
     torch.cuda.synchronize()
@@ -184,6 +186,47 @@ def test_native_checkpoint_loops_equal_explicit_steps(nsteps, segment):
     # the sweep sums every step's per-wave partials before one reduction:
     # the same terms in another order
     assert torch.allclose(ds, ds_ref, rtol=1e-12, atol=1e-14 * float(ds_ref.abs().max()))
+    sv.close()
+
+
+def test_two_stream_sweep_equals_one_stream_sweep():
+    """The sweep with two sets of work buffers (recomputation on the
+    context's second stream, ordered by events) gives lam and ds bitwise
+    equal to the one-set sweep, on a 300 x 40 grid over 47 steps in segments
+    of 5 (ten segments, the last ragged), three calls in a row (the events
+    are reused); fewer work buffers than a segment needs are refused."""
+    rho, T, s, dt, dx, dy = _small_case(300, 40, seed=5)
+    ny, nx = rho.shape
+    sv = Solver(nx, ny, "fp32_eq64")
+    sv.set_params(1.4, s, dt, dx, dy)
+    r0, T0 = torch.tensor(rho, device="cuda"), torch.tensor(T, device="cuda")
+    zero = torch.zeros_like(r0)
+    nsteps, segment = 47, 5
+    f, tmp = sv.empty_state(), sv.empty_state()
+    sv.init_buffer(r0, zero, zero, T0, f)
+    ck = [sv.empty_state() for _ in range((nsteps + segment - 1) // segment)]
+    sv.step_checkpointed(f, tmp, segment, nsteps, ck)
+    lamN = np.random.default_rng(7).standard_normal((16, ny, nx))
+    out = {}
+    for sets in (1, 2):
+        work = [sv.empty_state() for _ in range(sets * (segment - 1))]
+        for call in range(3):
+            print(f"sets {sets} call {call}", flush=True)
+            lam, lam2 = _padded(sv, lamN), sv.empty_state()
+            ds = torch.zeros(16, dtype=torch.float64, device="cuda")
+            sv.adjoint_sweep(ck, segment, nsteps, work, lam, lam2, ds)
+            torch.cuda.synchronize()
+            got = (_unpadded_t(sv, lam).clone(), ds.clone())
+            if sets in out:
+                assert torch.equal(got[0], out[sets][0]) and torch.equal(got[1], out[sets][1])
+            out[sets] = got
+    assert torch.equal(out[1][0], out[2][0])
+    assert torch.equal(out[1][1], out[2][1])
+    lam, lam2 = _padded(sv, lamN), sv.empty_state()
+    ds = torch.zeros(16, dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError, match="work buffers"):
+        sv.adjoint_sweep(ck, segment, nsteps, [sv.empty_state() for _ in range(segment - 2)],
+                         lam, lam2, ds)
     sv.close()
 
 
