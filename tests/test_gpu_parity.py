@@ -107,6 +107,29 @@ def test_bitwise_deterministic():
     assert np.array_equal(outs[0], outs[1])
 
 
+@pytest.mark.parametrize("per_pass,bc,ny", [(1, ("eq", "outflow", "reflect", "reflect"), 37),
+                                             (2, ("eq", "outflow", "reflect", "reflect"), 37),
+                                             (4, ("eq", "eq", "periodic", "periodic"), 4)])
+def test_zero_steps_change_nothing(per_pass, bc, ny):
+    """The degenerate call step(0) launches nothing on any path (one, two or
+    four steps per pass): the populations stay bit for bit, and the next
+    steps (7: passes and a remainder) still agree with the oracle to 1e-12
+    in FP64."""
+    case = smooth_case(300, ny, bc, seed=23)
+    print(f"case {case.name} per_pass {per_pass} zero steps", flush=True)
+    s = solver_for_case(case, "fp64")
+    s.set_steps_per_pass(per_pass, 0)
+    before = s.populations()
+    s.step(0)
+    assert np.array_equal(s.populations(), before)
+    s.step(7)
+    s.step(0)
+    want, _ = oracle_run(case, 7)
+    got = s.populations()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.abs(want).max()
+    s.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32_eq64"])
 def test_graph_replays_equal_plain_launches(precision):
     """mrt_step(n) for n > 1 replays captured graphs (64-step chunks plus a
