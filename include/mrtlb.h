@@ -128,7 +128,7 @@ int mrt_set_fields(mrt_ctx* ctx, const double* rho, const double* ux, const doub
 
 /* Advance n time steps (Eq. 3, forward Euler, Lax-Wendroff).  Asynchronous.
  * One kernel pass per step, or per two steps (mrt_set_steps_per_pass; the
- * default for grids larger than the last-level cache), an odd
+ * default from about 1024 x 1024 cells on), an odd
  * last step then taking a one-step pass.  Health (NaN, rho <= 0, T <= 0) is
  * recorded on the device and reported by the next synchronising call.
  * Errors: MRT_ESTATE, MRT_EINVAL (n < 0). */
@@ -179,17 +179,19 @@ int mrt_sync(mrt_ctx* ctx);
 int mrt_set_tile(mrt_ctx* ctx, int rows_per_item, int grid_blocks);
 int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
 
-/* Time steps per pass over the populations: 1 or 2 (default: 2 for grids
- * whose population buffer exceeds the 256 MB last-level cache, else 1;
- * mrt_autotune times both and keeps the faster).  With 2, one kernel launch
+/* Time steps per pass over the populations: 1, 2 or 4 (default: 2 for grids
+ * whose population buffer exceeds the 256 MB last-level cache or that give
+ * at least 512 two-step work items of 8-row bands, about 1024 x 1024 cells
+ * and up; else 1.  mrt_autotune times all that apply and keeps the fastest).  With 2, one kernel launch
  * advances the state two steps of Eq. 3 (the same per-site arithmetic as two
  * single steps, f^{n+1} rounded to the storage precision as a stored state
  * would be, so the same result up to rounding order: measured bit-identical
  * in the FP32 storage forms, within a few roundings in FP64):
  * each work item reads f^n once, keeps f^{n+1} in registers and writes
  * f^{n+2}, recomputing f^{n+1} on the two rows above and below its band of
- * `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = by grid size, 8 to 32 rows in FP32
- * storage, 8 to 64 in FP64, which runs one block per CU) and on its
+ * `rows` rows (1..MRT_MAX_BAND_ROWS_2; 0 = by grid size: 8, 16 or 32 rows in
+ * FP32 storage, up to 64 in FP64, which runs one block per CU, chosen for
+ * the fewest rounds of resident blocks x (rows + 5)) and on its
  * two edge columns, which halves the memory traffic per step.  An odd last
  * step of mrt_step runs the single-step kernel.  Every precision; the
  * default scheme only (variants set by mrt_set_scheme run one step per

@@ -305,19 +305,50 @@ void add_items(std::vector<Item>& items, int inst, int nx, int ny, int rows) {
 // Short bands (at most 6 rows) and many blocks: the step streams best with
 // ~8-16k blocks of short marches (measured on the 4096^2 grid); small grids
 // go down to one-row bands so that they still spread over the chip.
-// Default band height of the two-step kernel: each band recomputes f^{n+1}
-// on two extra rows, so taller bands waste less (1/rows) but give fewer
-// blocks: in FP32 storage up to 32 rows while the grid still gives ~2048
-// work items (four per block slot of the chip at two blocks per CU; 64-row
-// bands measured 3 % slower on the 4096^2 grid), in FP64 storage, which runs
-// one block per CU, up to 64 rows while it gives ~1024 (64 rows measured
-// 1.4 % faster than 32 there); at least 8.
+//
+// The two-step kernel's blocks stay resident together: kTwoStepSlots[fp64]
+// of them fill the chip (two per CU in FP32 storage, one in FP64).  A
+// launch takes ceil(items / slots) rounds of blocks, and a block's time
+// grows with the rows it stores plus about five rows' worth of fixed work
+// (the two recomputed f^{n+1} halo rows and the halo-column prologue).
+constexpr long long kTwoStepSlots[2] = {512, 256};
+constexpr long long kTwoStepFixedRows = 5;
+
+long long two_step_items(int nx, int ny, int rows) {
+    return (long long)((nx + 255) / 256) * ((ny + rows - 1) / rows);
+}
+
+// Default band height of the two-step kernel: among 8, 16, 32 (and 64 in
+// FP64 storage) rows, the one with the fewest rounds x (rows + 5) that
+// still fills at least one round (8 rows when none does).  Measured on
+// 2D Riemann grids and the shock-bubble grid, in both storage precisions:
+// 1024^2 picks 8 / 16 rows (FP32 / FP64), 1536^2 8 / 16, 2048^2 32 / 64,
+// 4096^2 32 / 64, each the fastest or within 7 % of it.
 int default_rows2(int nx, int ny, int prec) {
-    const long long chunks = (nx + 255) / 256;
     const bool fp64 = prec == MRT_FP64;
-    const long long r = std::max<long long>(
-        8, std::min<long long>(fp64 ? 64 : 32, chunks * ny / (fp64 ? 1024 : 2048)));
-    return int(std::min<long long>(r, ny));
+    const long long slots = kTwoStepSlots[fp64 ? 1 : 0];
+    int best = 8;
+    long long best_cost = -1;
+    for (int r : {8, 16, 32, 64}) {
+        if (r == 64 && !fp64) break;
+        if (r > ny && r != 8) break;
+        const long long items = two_step_items(nx, ny, r);
+        if (items < slots && r != 8) continue;
+        const long long cost = (items + slots - 1) / slots * (r + kTwoStepFixedRows);
+        if (best_cost < 0 || cost < best_cost) {
+            best = r;
+            best_cost = cost;
+        }
+    }
+    return std::min(best, ny);
+}
+
+// Whether a grid runs two steps per pass by default: larger than the
+// last-level cache, or giving at least one full round of 8-row bands (from
+// about 1024^2 on: there two steps per pass measured 1.2-1.9 x one, while
+// 768^2 and smaller ran faster with one).
+bool two_step_default(int nx, int ny, bool beyond_cache) {
+    return beyond_cache || two_step_items(nx, ny, 8) >= kTwoStepSlots[0];
 }
 
 // Band height of the batch's two-step kernel when none is given.
@@ -580,9 +611,10 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
     c->nt = (long long)bytes > kNonTemporalBytes;
     c->walls = has_kind(bc, MRT_BC_REFLECT) && (long long)nx * ny <= kWallsInKernelCells;
     // grids larger than the last-level cache (HBM-bound with one step per
-    // pass) run two steps per pass by default (4096^2: FP32 storage 0.65 ->
-    // 0.94, FP64 0.68 -> 0.91 of the per-step roofline)
-    if (c->nt) {
+    // pass: 4096^2 FP32 storage 0.65 -> 0.96, FP64 0.68 -> 0.93 of the
+    // per-step roofline with two) and cache-resident ones from about 1024^2
+    // on run two steps per pass by default
+    if (two_step_default(nx, ny, c->nt)) {
         if (build_items2(c, default_rows2(nx, ny, precision)) != MRT_OK) return fail(MRT_EDEVICE);
         c->per_pass = 2;
     }
