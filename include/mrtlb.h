@@ -179,10 +179,11 @@ int mrt_sync(mrt_ctx* ctx);
 int mrt_set_tile(mrt_ctx* ctx, int rows_per_item, int grid_blocks);
 int mrt_get_tile(const mrt_ctx* ctx, int* rows_per_item, int* grid_blocks);
 
-/* Time steps per pass over the populations: 1, 2 or 4 (default: 2 for grids
- * whose population buffer exceeds the 256 MB last-level cache or that give
- * at least 512 two-step work items of 8-row bands, about 1024 x 1024 cells
- * and up; else 1.  mrt_autotune times all that apply and keeps the fastest).  With 2, one kernel launch
+/* Time steps per pass over the populations: 1, 2 or 4 (default: 4 for the
+ * grids the tube march below covers; 2 for grids whose population buffer
+ * exceeds the 256 MB last-level cache or that give at least 512 two-step
+ * work items of 8-row bands, about 1024 x 1024 cells and up; else 1.
+ * mrt_autotune times all that apply and keeps the fastest).  With 2, one kernel launch
  * advances the state two steps of Eq. 3 (the same per-site arithmetic as two
  * single steps, f^{n+1} rounded to the storage precision as a stored state
  * would be, so the same result up to rounding order: measured bit-identical
@@ -371,8 +372,9 @@ int mrt_batch_get_populations(mrt_batch* b, int i, double* f);
  * the fastest.  Changing the tile drops the captured graphs. */
 int mrt_batch_set_tile(mrt_batch* b, int rows_per_item, int grid_blocks);
 int mrt_batch_get_tile(const mrt_batch* b, int* rows_per_item, int* grid_blocks);
-/* As mrt_set_steps_per_pass, for every instance of the batch (default 1;
- * rows 0 = 32, bands never exceed an instance's height).  steps = 4: the
+/* As mrt_set_steps_per_pass, for every instance of the batch (default 4 on
+ * a batch the tube march covers, else 1; rows 0 = 32, bands never exceed an
+ * instance's height).  steps = 4: the
  * tube march, for batches whose instances all have the same height of 1, 2
  * or 4 periodic rows and fixed-equilibrium x sides (the shock tubes of
  * section (b)), any precision.  Synchronises.

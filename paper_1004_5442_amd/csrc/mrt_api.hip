@@ -618,6 +618,12 @@ int mrt_init_grid(mrt_ctx** out, int nx, int ny, int precision, const int bc[4],
         if (build_items2(c, default_rows2(nx, ny, precision)) != MRT_OK) return fail(MRT_EDEVICE);
         c->per_pass = 2;
     }
+    // grids the tube march covers (1, 2 or 4 periodic rows, fixed-equilibrium
+    // x sides: the shock tubes) run four steps per pass by default
+    if (tube_inst_ok(c->inst)) {
+        if (build_items4(c) != MRT_OK) return fail(MRT_EDEVICE);
+        c->per_pass = kTubeSteps;
+    }
     (void)ctx_err;
     *out = c;
     return MRT_OK;
@@ -1477,6 +1483,13 @@ int mrt_batch_create(mrt_batch** out, int count, const mrt_instance* desc, int p
         hipMemset(b->d_health, 0, sizeof(unsigned)) != hipSuccess)
         return fail(MRT_EDEVICE);
     if (batch_items(b, std::min(maxny, 64)) != MRT_OK) return fail(MRT_EDEVICE);
+    // a batch of tubes the tube march covers (all of one height of 1, 2 or 4
+    // periodic rows, fixed-equilibrium x sides) runs four steps per pass by
+    // default
+    if (tube_march_ok(b)) {
+        if (batch_items4(b) != MRT_OK) return fail(MRT_EDEVICE);
+        b->per_pass = kTubeSteps;
+    }
     if (hipMemcpy(b->d_insts, b->insts.data(), sizeof(Inst) * count, hipMemcpyHostToDevice) != hipSuccess)
         return fail(MRT_EDEVICE);
     (void)ctx_err;

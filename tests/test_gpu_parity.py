@@ -58,11 +58,15 @@ def test_fp32_forms_match_oracle_fields(precision, bc):
     assert max(err.values()) < 1e-5, err
 
 
-def test_sod_tube_fp64_1000_steps():
-    """Plain method, FP64: the 400x4 Sod tube for 1000 steps."""
+@pytest.mark.parametrize("per_pass", [1, 4])
+def test_sod_tube_fp64_1000_steps(per_pass):
+    """Plain method, FP64: the 400x4 Sod tube for 1000 steps, one step per
+    pass and by the tube march (this grid's default)."""
     case = W.sod_tube()
     want, p = oracle_run(case, case.nsteps)
     s = solver_for_case(case, "fp64")
+    assert s.steps_per_pass() == (4, 4)
+    s.set_steps_per_pass(per_pass, 0)
     s.step(case.nsteps)
     err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
     print("sod fp64", err)

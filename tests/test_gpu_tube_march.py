@@ -51,7 +51,9 @@ def test_tube_march_matches_oracle_and_single_steps(precision):
     the bound is two FP32 ulps of the population scale."""
     cases = _tubes(SIZES)
     one = Batch(cases, precision)
+    one.set_steps_per_pass(1)             # the batch of tubes defaults to the tube march
     tube = Batch(cases, precision)
+    assert tube.steps_per_pass() == (4, 4)
     tube.set_steps_per_pass(4)
     assert tube.steps_per_pass() == (4, 4)
     for call in range(3):
@@ -78,6 +80,7 @@ def test_tube_march_across_graph_replays_and_step_counts():
     per pass."""
     cases = _tubes([300, 600], seed=5)
     one = Batch(cases, "fp32")
+    one.set_steps_per_pass(1)
     tube = Batch(cases, "fp32")
     tube.set_steps_per_pass(4)
     for n in (1, 2, 3, 4, 7, 258):
@@ -97,6 +100,7 @@ def test_tube_march_fp64_matches_oracle_and_single_steps(ny):
     the two kernels)."""
     cases = _tubes([3, TUBE_WIDTH, TUBE_WIDTH + 1, 600], seed=7, ny=ny)
     one = Batch(cases, "fp64")
+    one.set_steps_per_pass(1)
     tube = Batch(cases, "fp64")
     tube.set_steps_per_pass(4)
     assert tube.steps_per_pass() == (4, ny)
@@ -121,6 +125,7 @@ def test_tube_march_one_and_two_rows_fp32(ny):
     FP32-storage error) and against one step per pass (two FP32 ulps)."""
     cases = _tubes([200, TUBE_WIDTH + 1, 745], seed=4, ny=ny)
     one = Batch(cases, "fp32_eq64")
+    one.set_steps_per_pass(1)
     tube = Batch(cases, "fp32_eq64")
     tube.set_steps_per_pass(4)
     one.step(41)

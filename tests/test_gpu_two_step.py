@@ -23,7 +23,7 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("needs the GPU", allow_module_level=True)
 
-from paper_1004_5442_amd.solver import solver_for_case  # noqa: E402
+from paper_1004_5442_amd.solver import Solver, solver_for_case  # noqa: E402
 
 BC_SETS = [
     ("periodic", "periodic", "periodic", "periodic"),
@@ -213,6 +213,34 @@ def test_default_and_autotuned_path():
     err = field_errors(s.moments(), mrt.macroscopic(want, p.b))
     assert max(err.values()) < 1e-5, err
     s.close()
+
+
+def test_default_launch_shapes():
+    """The launch a grid gets without autotuning: one step per pass below
+    about 1024^2 cells, two from there on (8- or 16-row bands, by storage
+    precision), 32 / 64 rows at 4096^2, and the tube march on the shock
+    tubes it covers, single or batched."""
+    from paper_1004_5442_amd.batch import Batch
+    bc = ("outflow",) * 4
+    expect = [(768, "fp32_eq64", (1,)), (1024, "fp32_eq64", (2, 8)), (1024, "fp64", (2, 16)),
+              (2048, "fp32_eq64", (2, 32)), (2048, "fp64", (2, 64))]
+    for n, prec, want in expect:
+        s = Solver(n, n, prec, bc)
+        got = s.steps_per_pass()
+        print(n, prec, got, flush=True)
+        assert got[:len(want)] == want, (n, prec, got)
+        s.close()
+    tube = W.sod_tube()
+    s = solver_for_case(tube, "fp32_eq64")
+    assert s.steps_per_pass() == (4, 4)
+    s.close()
+    b = Batch(W.tube_batch(6, seed=2, nx_range=(200, 300)), "fp32_eq64")
+    assert b.steps_per_pass() == (4, 4)
+    b.close()
+    mixed = W.tube_batch(2, seed=2, nx_range=(200, 300)) + [smooth_case(64, 5, bc, seed=1)]
+    b = Batch(mixed, "fp32_eq64")
+    assert b.steps_per_pass()[0] == 1
+    b.close()
 
 
 @pytest.mark.parametrize("bc", [("reflect", "reflect", "reflect", "reflect"),
