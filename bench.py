@@ -264,7 +264,8 @@ def time_adjoint_large(n, steps):
 def time_adjoint(steps):
     """Adjoint step vs forward step on the 256^2 periodic adjoint workload
     (FP32 storage, FP64 collision), and one full gradient (500-step forward,
-    sqrt(N) checkpoints, backward) vs the plain 500-step forward."""
+    sqrt(N) checkpoints, backward) vs the plain 500-step forward (each the
+    median of five runs)."""
     import torch
 
     from paper_1004_5442_amd import workloads as W
@@ -301,22 +302,29 @@ def time_adjoint(steps):
     s0 = torch.tensor(case.s, device="cuda")
     with torch.no_grad():
         target = density_after(rho0, torch.tensor(T_target, device="cuda"), s0, sv, *args)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    with torch.no_grad():
-        density_after(rho0, T0, s0, sv, *args)
-    torch.cuda.synchronize()
-    t_fwd_full = time.perf_counter() - t0
+    def fwd_full():
+        with torch.no_grad():
+            density_after(rho0, T0, s0, sv, *args)
+        torch.cuda.synchronize()
+
     def grad():
         r = rho0.clone().requires_grad_(True)
         L = 0.5 * ((density_after(r, T0, s0, sv, *args) - target) ** 2).sum()
         L.backward()
         torch.cuda.synchronize()
 
+    def median_s(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return sorted(ts)[reps // 2]
+
+    torch.cuda.synchronize()
+    t_fwd_full = median_s(fwd_full)
     grad()          # the first backward also starts autograd's device threads
-    t0 = time.perf_counter()
-    grad()
-    t_grad = time.perf_counter() - t0
+    t_grad = median_s(grad)
     sv.close()
     return {"grid": f"{n}x{n}", "adjoint_step_ms": round(1e3 * t_a, 4), "forward_step_ms": round(1e3 * t_f, 4),
             "adjoint_over_forward": round(t_a / t_f, 3),

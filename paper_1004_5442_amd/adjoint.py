@@ -36,7 +36,7 @@ class DensityMap(torch.autograd.Function):
                 gamma: float, dt: float, dx: float, dy: float, nsteps: int,
                 segment: Optional[int] = None):
         sv = s.detach().to("cpu", torch.float64)
-        solver.set_params(gamma, sv.tolist(), dt, dx, dy, 0.0)
+        solver.ensure_params(gamma, sv.tolist(), dt, dx, dy, 0.0)
         if not any(ctx.needs_input_grad[:3]):
             K = max(1, nsteps)        # no backward to come: one checkpoint, f^0
         else:
@@ -65,7 +65,10 @@ class DensityMap(torch.autograd.Function):
         solver, K, N = ctx.solver, ctx.K, ctx.nsteps
         rho0d, T0d = ctx.saved_tensors
         gamma, s_list, dt, dx, dy = ctx.params
-        solver.set_params(gamma, s_list, dt, dx, dy, 0.0)
+        # only if another forward or a caller changed them since (setting
+        # them waits for the stream: the forward's steps would drain before
+        # the backward's launches are queued)
+        solver.ensure_params(gamma, s_list, dt, dx, dy, 0.0)
         lam, lam2 = solver.empty_state(), solver.empty_state()
         solver.density_adjoint(g_rhoN.detach().to(torch.float64).contiguous(), lam)
         ds = torch.zeros(16, dtype=torch.float64, device=rho0d.device)

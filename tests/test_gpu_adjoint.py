@@ -331,4 +331,24 @@ def test_backward_uses_the_parameters_of_its_own_forward():
     a = grad(False)
     b = grad(True)
     assert np.array_equal(a, b)
+    # parameters are set again only where they changed: a backward right
+    # after its own forward sets none (setting them waits for the stream)
+    calls = []
+    orig = Solver.set_params
+
+    def counted(self, *args, **kw):
+        calls.append(args)
+        return orig(self, *args, **kw)
+
+    Solver.set_params = counted
+    try:
+        c = grad(False)      # the last backward left s set: none
+        assert len(calls) == 0, calls
+        d = grad(False)
+        assert len(calls) == 0, calls
+        e = grad(True)       # the second forward (s2), then the backward (s): two
+        assert len(calls) == 2, calls
+    finally:
+        Solver.set_params = orig
+    assert np.array_equal(a, c) and np.array_equal(a, d) and np.array_equal(a, e)
     sv.close()
