@@ -1178,11 +1178,13 @@ int mrt_step_checkpointed(mrt_ctx* c, void* f, void* f_tmp, int segment, int nst
 static int ensure_aux_stream(mrt_ctx* c) {
     std::string& ctx_err = c->err;
     if (c->aux) return MRT_OK;
+    // the events first: the stream is the flag that all of them exist (the
+    // ones made before a failure are kept and reused by the next attempt)
+    for (hipEvent_t* e : {&c->ev_fork, &c->ev_rec[0], &c->ev_rec[1], &c->ev_adj[0], &c->ev_adj[1]})
+        if (!*e) HIPTRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     hipStream_t st = nullptr;
     HIPTRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
     c->aux = st;
-    for (hipEvent_t* e : {&c->ev_fork, &c->ev_rec[0], &c->ev_rec[1], &c->ev_adj[0], &c->ev_adj[1]})
-        HIPTRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return MRT_OK;
 }
 
